@@ -1,0 +1,68 @@
+"""Diagnostics of a spectral state (energies, divergence, wall slip).
+
+Volume integrals use trapezoid weights on the radial nodes and Parseval in
+(theta, z): a real field's mean square over a (theta, z) plane is
+sum_{l,n} c_n |f_ln|^2 with c_0 = 1 and c_n = 2 for n > 0 (the n < 0 half
+is the complex conjugate of the stored one).
+"""
+import numpy as np
+
+from .radial import couette_profile
+
+
+def trapezoid_weights(r):
+    w = np.zeros_like(r)
+    h = np.diff(r)
+    w[:-1] += h / 2.0
+    w[1:] += h / 2.0
+    return w
+
+
+def plane_energy_density(prob, u):
+    """Per-node sum_{l,n} c_n ((|u+|^2 + |u-|^2)/2 + |u_z|^2)/2 -> (n_r,)."""
+    c = np.full(prob.m_theta, 2.0)
+    c[0] = 1.0
+    dens = 0.5 * (np.abs(u[0]) ** 2 + np.abs(u[1]) ** 2) + np.abs(u[2]) ** 2
+    dens[:, prob.nyq, :] = 0.0
+    return 0.5 * np.einsum("jsn,n->j", dens, c)
+
+
+def energy(prob, u):
+    """Kinetic energy 1/2 int |u|^2 r dr dtheta dz over the periodic box."""
+    area = (2.0 * np.pi / prob.k_theta) * (2.0 * np.pi / prob.k_z)
+    w = trapezoid_weights(prob.r)
+    return area * np.sum(w * prob.r * plane_energy_density(prob, u))
+
+
+def couette_state(prob):
+    """Circular Couette flow in the stored layout: u+- = +-i U_theta at mode (0,0)."""
+    u = prob.zeros(3)
+    U = couette_profile(prob.r, prob.eta, prob.Re_i, prob.Re_o)
+    u[0, :, 0, 0] = 1j * U
+    u[1, :, 0, 0] = -1j * U
+    return u
+
+
+def perturbation_energy(prob, u):
+    return energy(prob, u - couette_state(prob))
+
+
+def wall_slip(prob, u, wall=0):
+    """Tangential slip at a wall relative to Re: sqrt(<(u_theta - Re)^2 + u_z^2>).
+
+    The integrand printed in Sec. 5.3 has (u_theta - Re_i)^2 - u_z^2 under
+    the root; the minus sign is read as a plus (a norm of the tangential
+    velocity error).
+    """
+    Re = prob.Re_i if wall == 0 else prob.Re_o
+    j = 0 if wall == 0 else -1
+    ut = -0.5j * (u[0, j] - u[1, j])
+    uz = u[2, j].copy()
+    ut = ut.copy()
+    ut[0, 0] -= Re
+    c = np.full(prob.m_theta, 2.0)
+    c[0] = 1.0
+    ut[prob.nyq] = 0.0
+    uz[prob.nyq] = 0.0
+    ms = np.sum(c * (np.abs(ut) ** 2 + np.abs(uz) ** 2))
+    return np.sqrt(ms) / abs(Re)

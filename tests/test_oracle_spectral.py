@@ -1,0 +1,129 @@
+"""Pins of the oracle's pseudospectral nonlinear term (Sec. 3.2, step 1)."""
+import numpy as np
+import pytest
+
+import oracle
+import tc_inputs
+from oracle import nonlinear as nl
+
+
+def _tiny(m_theta=4, m_z=6, n_r=9):
+    return oracle.Problem(n_r, m_theta, m_z, 0.5, 10.0, 0.0, 1e-3, k_theta=2.0, k_z=1.5)
+
+
+def _full_spectrum(P, f):
+    """Dict (l, n) -> coefficient over the full +-n range of a real field."""
+    out = {}
+    for s in range(P.m_z):
+        if s == P.nyq:
+            continue
+        l = int(P.l[s])
+        for n in range(P.m_theta):
+            out[(l, n)] = f[s, n]
+            if n > 0:
+                out[(-l, -n)] = np.conj(f[s, n])
+    return out
+
+
+def test_transform_matches_direct_dft():
+    P = _tiny()
+    f = tc_inputs.random_state((P.m_z, P.m_theta), 7)
+    g = nl.to_physical(P, f)
+    zz = 2 * np.pi * np.arange(P.p_z) / P.p_z
+    tt = 2 * np.pi * np.arange(P.p_theta) / P.p_theta
+    direct = np.zeros((P.p_z, P.p_theta), dtype=complex)
+    for (l, n), c in _full_spectrum(P, f).items():
+        direct += c * np.exp(1j * (l * zz[:, None] + n * tt[None, :]))
+    assert np.abs(direct.imag).max() < 1e-13
+    np.testing.assert_allclose(g, direct.real, rtol=0, atol=1e-13)
+
+
+def test_transform_roundtrip_and_parseval():
+    P = oracle.Problem(8, 16, 32, 0.5, 10.0, 0.0, 1e-3)
+    f = tc_inputs.random_state((3, P.m_z, P.m_theta), 11)
+    g = nl.to_physical(P, f)
+    np.testing.assert_allclose(nl.to_spectral(P, g), f, rtol=0, atol=1e-14)
+    c = np.full(P.m_theta, 2.0)
+    c[0] = 1.0
+    ms_spec = np.einsum("ksn,n->k", np.abs(f) ** 2, c)
+    np.testing.assert_allclose(np.mean(g ** 2, axis=(-2, -1)), ms_spec, rtol=1e-13)
+
+
+def test_dealiased_product_equals_truncated_convolution():
+    P = _tiny(m_theta=5, m_z=8)
+    f = tc_inputs.random_state((P.m_z, P.m_theta), 3)
+    g = tc_inputs.random_state((P.m_z, P.m_theta), 4)
+    prod = nl.to_spectral(P, nl.to_physical(P, f) * nl.to_physical(P, g))
+    F, G = _full_spectrum(P, f), _full_spectrum(P, g)
+    for s in range(P.m_z):
+        if s == P.nyq:
+            assert prod[s].max() == 0
+            continue
+        l = int(P.l[s])
+        for n in range(P.m_theta):
+            ref = sum(cf * G.get((l - l1, n - n1), 0.0) for (l1, n1), cf in F.items())
+            assert abs(prod[s, n] - ref) < 1e-13
+
+
+def test_curl_exact_on_polynomial_profiles():
+    # every FD row (5 to 9 points) differentiates quartics exactly, so the
+    # oracle's omega must equal the analytic curl for such profiles
+    P = oracle.Problem(20, 6, 8, 0.6, 10.0, 0.0, 1e-3, k_theta=3.0, k_z=0.7)
+    rng = np.random.Generator(np.random.PCG64(5))
+    coef = rng.standard_normal((3, 5, P.m_z, P.m_theta)) + 1j * rng.standard_normal((3, 5, P.m_z, P.m_theta))
+    r = P.r
+    pw = np.stack([r ** k for k in range(5)])
+    dpw = np.stack([k * r ** (k - 1) if k else 0 * r for k in range(5)])
+    ur, ut, uz = (np.einsum("kj,ksn->jsn", pw, coef[c]) for c in range(3))
+    dut, duz = (np.einsum("kj,ksn->jsn", dpw, coef[c]) for c in (1, 2))
+    u = np.stack([ur + 1j * ut, ur - 1j * ut, uz])
+    a, b, rr = P.bcast()
+    exact = (1j * a * uz / rr - 1j * b * ut, 1j * b * ur - duz, dut + ut / rr - 1j * a * ur / rr)
+    got = nl.vorticity(P, u)
+    for e, g in zip(exact, got):
+        np.testing.assert_allclose(g, e, rtol=0, atol=1e-10 * np.abs(e).max())
+
+
+def _plane_work(P, u, N):
+    c = np.full(P.m_theta, 2.0)
+    c[0] = 1.0
+    dens = 0.5 * (np.conj(u[0]) * N[0] + np.conj(u[1]) * N[1]) + np.conj(u[2]) * N[2]
+    return np.einsum("n,jsn->j", c, dens.real)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_energy_neutrality(seed):
+    # int u.(omega x u) = 0 holds exactly on every radial node because the
+    # 3/2 rule keeps the retained coefficients of the product exact
+    cfg = dict(tc_inputs.CONFIGS["small"])
+    cfg["envelope"] = "k53"
+    cfg["seed"] = seed
+    cfg["amp"] = 0.3
+    P = oracle.Problem(cfg["n_r"], cfg["m_theta"], cfg["m_z"], cfg["eta"], cfg["Re_i"], cfg["Re_o"], cfg["dt"])
+    u = tc_inputs.initial_state(P.r, cfg)
+    N = oracle.nonlinear_rot(P, u)
+    w = _plane_work(P, u, N)
+    assert np.abs(w).max() <= 1e-13 * np.linalg.norm(u) * np.linalg.norm(N)
+    # a planted error (u_theta component dropped from N_r) breaks it
+    U = nl.to_physical(P, np.stack(nl.cylindrical(u)))
+    W = nl.to_physical(P, np.stack(nl.vorticity(P, u)))
+    S = nl.to_spectral(P, np.stack([W[1] * U[2], W[2] * U[0] - W[0] * U[2], W[0] * U[1] - W[1] * U[0]]))
+    bad = _plane_work(P, u, nl.plus_minus(*S))
+    assert np.abs(bad).max() > 1e-6 * np.linalg.norm(u) * np.linalg.norm(N)
+
+
+def test_rotational_matches_convective_up_to_bernoulli_gradient():
+    # u.grad u = omega x u + grad(|u|^2/2); discretely the difference is FD
+    # error, which must shrink at high order as n_r grows
+    errs = []
+    for n_r in (24, 48):
+        cfg = dict(tc_inputs.CONFIGS["small"])
+        cfg.update(n_r=n_r, amp=0.2, m_theta=8, m_z=8)
+        P = oracle.Problem(n_r, 8, 8, cfg["eta"], cfg["Re_i"], cfg["Re_o"], cfg["dt"])
+        u = tc_inputs.initial_state(P.r, cfg)
+        K = nl.kinetic_density(P, u)
+        from oracle.scheme import grad
+        diff = nl.nonlinear_conv(P, u) - nl.nonlinear_rot(P, u) - grad(P, K)
+        errs.append(np.abs(diff).max() / np.abs(nl.nonlinear_conv(P, u)).max())
+    assert errs[1] < errs[0] / 2 ** 6, errs
+    assert errs[1] < 1e-4
