@@ -1,0 +1,110 @@
+// Internal definitions shared by the translation units of libtc.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tc.h"
+#include "tc_fft.h"
+
+namespace tc {
+
+using cd = C2<double>;
+using cf = C2<float>;
+
+// Radial stencil half-width (9-point central stencils, Sec. 3.1).
+constexpr int HW = 4;
+constexpr int NB9 = 2 * HW + 1;
+
+// Per-node constants read by every radial kernel (wave-uniform loads):
+// r, 1/r, 1/r^2, D1 row weights (9), D2 row weights (9).  Weight k of
+// row j multiplies node j + k - 4 (zero outside the shortened stencil).
+constexpr int RC_R = 0, RC_IR = 1, RC_IR2 = 2, RC_W1 = 3, RC_W2 = 12, RC_N = 21;
+
+// Factor storage: fac[op][j][c][dm], dm = |l| * m_theta + n a distinct mode
+// (the slots +l and -l share one factorisation).  op 0 = P (pressure and
+// correction), factored in ascending row order; ops 1-3 = H+, H-, H_z,
+// factored in descending row order.  For row j, in the op's own row order:
+//   c = 0..3  first-sweep multipliers of the rows 1..4 places earlier,
+//   c = 4     1 / pivot,
+//   c = 5..8  second-sweep coefficients of the rows 1..4 places later.
+constexpr int NOPS = 4, NFAC = 9;
+enum { OP_P = 0, OP_HP = 1, OP_HM = 2, OP_HZ = 3 };
+
+// Launch timing slots (tc_kernel_time).
+enum { TK_PC = 0, TK_CURL = 1, TK_ZINV = 2, TK_THETA = 3, TK_ZFWD = 4, TK_N = 5 };
+
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;  // pairs
+  int used = 0;
+  double ms = 0.0;
+  int launches = 0;
+};
+
+struct Dims {
+  int n_r, mt, mz, pt, pz, nyq, half, ndm;
+  int64_t S;      // m_z * m_theta (one radial plane of one field)
+  int64_t F;      // n_r * S (one field)
+  double kt, kz, dt, Re_i, Re_o;
+  double s0, sM;  // scale of the Neumann rows of P (rows 0 and M)
+};
+
+}  // namespace tc
+
+struct tc_ctx {
+  tc_grid g{};
+  tc::Dims d{};
+  double eta = 0, r_i = 0, r_o = 0;
+  hipStream_t stream = nullptr;
+  std::vector<double> r;    // host copy of the nodes
+  std::vector<double> rc;   // host copy of the per-node constants
+  // device data owned by the context
+  double* rc_dev = nullptr;
+  double* fac = nullptr;
+  tc::cd* tw_t = nullptr;   // exp(-2 pi i e / p_theta)
+  tc::cd* tw_z = nullptr;   // exp(-2 pi i e / p_z)
+  tc::cf* twf_t = nullptr;
+  tc::cf* twf_z = nullptr;
+  tc::cd* u = nullptr;       // u^i     (3 fields)
+  tc::cd* u_prev = nullptr;  // u^{i-1} (3 fields)
+  tc::cd* N_prev = nullptr;  // N^{i-1} (3 fields)
+  tc::cd* N_cur = nullptr;   // N^i     (3 fields)
+  tc::cd* p = nullptr;       // pressure (1 field)
+  tc::cd* omega = nullptr;   // curl work (3 fields)
+  tc::cd* aux = nullptr;     // adjoint work (allocated on first use)
+  size_t aux_bytes = 0;
+  void* inter = nullptr;     // nonlinear intermediate, batch planes
+  int batch = 0;
+  size_t bytes = 0;
+  int64_t steps = 0;
+  bool have_p = false;
+  bool timing = false;
+  tc::KernelTimer timers[tc::TK_N];
+  std::string err;
+};
+
+namespace tc {
+
+// error helpers
+tc_status fail(tc_ctx* c, tc_status s, const std::string& msg);
+tc_status hip_check(tc_ctx* c, hipError_t e, const char* what);
+
+// launchers (return hipError_t from hipGetLastError)
+hipError_t launch_factor(tc_ctx* c, int* bad_dev);
+hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x);
+hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev_scratch,
+                     cd* u_next, cd* p);
+hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
+hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
+hipError_t launch_theta(tc_ctx* c, int nplanes);
+hipError_t launch_zfwd(tc_ctx* c, int plane0, int nplanes, cd* N);
+bool fft_length_supported(int L);
+size_t inter_bytes_per_plane(const tc_ctx* c);
+
+// timing helpers (no-ops unless ctx->timing)
+void timer_begin(tc_ctx* c, int which);
+void timer_end(tc_ctx* c, int which);
+
+}  // namespace tc

@@ -1,0 +1,382 @@
+// Pseudospectral nonlinear term N = omega x u with 3/2 dealiasing (Sec. 3.2,
+// step 1 of the paper, rotational form).
+//
+// Complex-pair formulation.  With h = v_r + i v_theta, the full (+-n)
+// spectrum of h is  v+ (n >= 0)  and  conj(v-(-l, -n))  (n < 0), so u_r,
+// u_theta come out of ONE complex transform of (u+, u-), and likewise
+// omega_r, omega_theta from (omega+, omega-); u_z and omega_z are packed as
+// g = u_z + i omega_z.  In physical space
+//     N_r + i N_theta = i (omega_z h_u - u_z h_omega),
+//     N_z             = Im(conj(h_omega) h_u),
+// and the forward transform of N_r + i N_theta yields N+ on n >= 0 and
+// conj(N-(-l,-n)) on n < 0.  No +-/(r,theta) conversion is ever needed.
+// At n = 0 the two stored copies of a real field's coefficients (u+(l) and
+// conj(u-(-l))) are averaged, and the imaginary parts of u_z, omega_z are
+// dropped, which is what a real-to-complex transform does with an n = 0
+// bin: the result equals the plain transform of the cylindrical components
+// for every input, Hermitian or not.
+//
+// Kernels, per batch of radial planes:
+//   k_curl  : omega+, omega-, omega_z from u (radial D1 by the 9-point stencil),
+//             one lane per (l, n) marching through the radial nodes.
+//   k_zinv  : zero-pad and inverse-transform along z the 6 spectral fields
+//             (u+, u-, u_z, omega+, omega-, omega_z), NF columns per workgroup.
+//   k_theta : per z-row: assemble the 3 complex theta spectra, inverse
+//             transforms, products, forward transforms; writes the
+//             z-partial spectra of N+, N-, N_z over the first three inputs.
+//   k_zfwd  : forward z-transform, 1/(P_theta P_z) scaling, truncation to
+//             the stored modes.
+// Transform precision T is double, or float in the FP32-bulk form (the
+// spectral inputs and outputs stay double).
+#include "tc_internal.h"
+
+namespace tc {
+
+// ------------------------------------------------------------------ curl
+__global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dims d, const cd* __restrict__ u,
+                                              cd* __restrict__ w) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.S) return;
+  const int s = (int)(idx / d.mt), n = (int)(idx - (int64_t)s * d.mt);
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  if (s == d.nyq) {
+    for (int j = 0; j <= M; ++j) {
+      w[j * S + idx] = cd{0, 0};
+      w[F + j * S + idx] = cd{0, 0};
+      w[2 * F + j * S + idx] = cd{0, 0};
+    }
+    return;
+  }
+  const double a = n * d.kt;
+  const double b = (s < d.half ? s : s - d.mz) * d.kz;
+  cd wp[NB9], wm[NB9], wz[NB9];
+  for (int k = 0; k < NB9; ++k) wp[k] = wm[k] = wz[k] = cd{0, 0};
+  for (int j = 0; j <= M + HW; ++j) {
+    for (int k = 0; k < NB9 - 1; ++k) { wp[k] = wp[k + 1]; wm[k] = wm[k + 1]; wz[k] = wz[k + 1]; }
+    if (j <= M) {
+      const int64_t o = j * S + idx;
+      wp[NB9 - 1] = u[o]; wm[NB9 - 1] = u[F + o]; wz[NB9 - 1] = u[2 * F + o];
+    } else {
+      wp[NB9 - 1] = wm[NB9 - 1] = wz[NB9 - 1] = cd{0, 0};
+    }
+    const int i = j - HW;
+    if (i < 0) continue;
+    const double* R = rc + (int64_t)i * RC_N;
+    const double ir = R[RC_IR];
+    cd dp = {0, 0}, dmn = {0, 0}, dz = {0, 0};
+#pragma unroll
+    for (int k = 0; k < NB9; ++k) {
+      const double c = R[RC_W1 + k];
+      dp.x = fma(c, wp[k].x, dp.x); dp.y = fma(c, wp[k].y, dp.y);
+      dmn.x = fma(c, wm[k].x, dmn.x); dmn.y = fma(c, wm[k].y, dmn.y);
+      dz.x = fma(c, wz[k].x, dz.x); dz.y = fma(c, wz[k].y, dz.y);
+    }
+    const cd up = wp[HW], um = wm[HW], uz = wz[HW];
+    // omega+ = i (a/r uz - D1 uz) - b u+ ;  omega- = i (a/r uz + D1 uz) + b u-
+    const cd tp = {a * ir * uz.x - dz.x, a * ir * uz.y - dz.y};
+    const cd tm = {a * ir * uz.x + dz.x, a * ir * uz.y + dz.y};
+    const cd op = {-tp.y - b * up.x, tp.x - b * up.y};
+    const cd om = {-tm.y + b * um.x, tm.x + b * um.y};
+    // omega_z = -(i/2) [ (D1 + (1+a)/r) u+ - (D1 + (1-a)/r) u- ]
+    const cd q = {dp.x + (1.0 + a) * ir * up.x - dmn.x - (1.0 - a) * ir * um.x,
+                  dp.y + (1.0 + a) * ir * up.y - dmn.y - (1.0 - a) * ir * um.y};
+    const cd oz = {0.5 * q.y, -0.5 * q.x};
+    const int64_t o = i * S + idx;
+    w[o] = op;
+    w[F + o] = om;
+    w[2 * F + o] = oz;
+  }
+}
+
+hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
+  const int64_t blocks = (c->d.S + 255) / 256;
+  hipLaunchKernelGGL(k_curl, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, omega);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launch shapes
+// z kernels: NF columns per workgroup, TPF threads per column (NF * TPF threads).
+template <typename T, int L> struct ZShape {
+  static constexpr int TPF = L >= 512 ? 64 : (L >= 128 ? 32 : 8);
+  static constexpr int LDS_CAP = 98304;  // bytes of LDS a workgroup may take
+  static constexpr int NF0 = 256 / TPF;
+  static constexpr int NF1 = LDS_CAP / (L * (int)sizeof(C2<T>));
+  static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
+  static_assert(NF >= 1, "transform too long for LDS");
+};
+// theta kernel: TPF threads per row, RPB rows per workgroup.
+template <int L> struct TShape {
+  static constexpr int TPF = (L % 6 == 0) ? L / 6 : L / 8;
+  static constexpr int RPB = TPF >= 256 ? 1 : 256 / TPF;
+  static constexpr int PTS = L / TPF;
+};
+
+// Workgroup id -> logical tile: consecutive ids go to different XCDs (8 of
+// them, round robin), so remap to let each XCD walk a contiguous range of
+// tiles (neighbouring column tiles share cache lines).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int per = nblocks / 8;
+  if (per == 0 || bid >= per * 8) return bid;
+  return (bid % 8) * per + bid / 8;
+}
+
+// ------------------------------------------------------------------ z inverse
+template <typename T, int L>
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, const cd* __restrict__ u,
+                                                                             const cd* __restrict__ om,
+                                                                             C2<T>* __restrict__ inter,
+                                                                             const C2<T>* __restrict__ W) {
+  constexpr int NF = ZShape<T, L>::NF, TPF = ZShape<T, L>::TPF;
+  extern __shared__ unsigned char lds_raw[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+  const int tiles = (d.mt + NF - 1) / NF;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = bid % tiles;
+  const int rest = bid / tiles;
+  const int fld = rest % 6, pl = rest / 6;
+  const int f = threadIdx.x % NF, t = threadIdx.x / NF;
+  const int n = tile * NF + f;
+  const bool valid = n < d.mt;
+  const cd* src = (fld < 3 ? u + fld * d.F : om + (fld - 3) * d.F) + (int64_t)(plane0 + pl) * d.S;
+  const int h = d.half;
+  for (int e = t; e < L; e += TPF) {
+    int s = -1;
+    if (e < h) s = e;
+    else if (e > L - h) s = d.mz - (L - e);
+    C2<T> v = {T(0), T(0)};
+    if (s >= 0 && valid) {
+      const cd x = src[(int64_t)s * d.mt + n];
+      v = {T(x.x), T(x.y)};
+    }
+    buf[e * NF + f] = v;
+  }
+  __syncthreads();
+  fft_lds<T, L, NF, TPF, +1>(buf, W, t, f);
+  C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt;
+  if (valid)
+    for (int e = t; e < L; e += TPF) dst[(int64_t)e * d.mt + n] = buf[e * NF + f];
+}
+
+// ------------------------------------------------------------------ theta pass
+template <typename T>
+__device__ __forceinline__ C2<T> ld_inter(const C2<T>* row, int n) { return row[n]; }
+
+template <typename T, int L>
+__global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter,
+                                                                          const C2<T>* __restrict__ W) {
+  constexpr int TPF = TShape<L>::TPF, RPB = TShape<L>::RPB, PTS = TShape<L>::PTS;
+  extern __shared__ unsigned char lds_raw[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+  const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
+  const int64_t rows = (int64_t)nplanes * d.pz;
+  const int64_t row = (int64_t)blockIdx.x * RPB + f;
+  const bool valid = row < rows;
+  const int pl = valid ? (int)(row / d.pz) : 0;
+  const int z = valid ? (int)(row - (int64_t)pl * d.pz) : 0;
+  const int64_t fstride = (int64_t)d.pz * d.mt;  // one field of one plane
+  C2<T>* base = inter + (int64_t)pl * 6 * fstride + (int64_t)z * d.mt;
+  const int mt = d.mt;
+
+  C2<T> hu[PTS], hw[PTS], g[PTS];
+  for (int which = 0; which < 3; ++which) {
+    const C2<T>* A = base + (int64_t)(which == 0 ? 0 : (which == 1 ? 3 : 2)) * fstride;
+    const C2<T>* B = base + (int64_t)(which == 0 ? 1 : (which == 1 ? 4 : 5)) * fstride;
+    for (int e = t; e < L; e += TPF) {
+      const int nn = (e <= L / 2) ? e : e - L;
+      C2<T> v = {T(0), T(0)};
+      if (valid) {
+        if (which < 2) {
+          if (nn > 0 && nn < mt) v = A[nn];
+          else if (nn < 0 && -nn < mt) v = cconj(B[-nn]);
+          else if (nn == 0) {
+            const C2<T> p0 = A[0], m0 = B[0];
+            v = {T(0.5) * (p0.x + m0.x), T(0.5) * (p0.y - m0.y)};
+          }
+        } else {
+          // g = u_z + i omega_z; A = u_z column, B = omega_z column
+          if (nn > 0 && nn < mt) {
+            const C2<T> x = A[nn], y = B[nn];
+            v = {x.x - y.y, x.y + y.x};
+          } else if (nn < 0 && -nn < mt) {
+            const C2<T> x = cconj(A[-nn]), y = cconj(B[-nn]);
+            v = {x.x - y.y, x.y + y.x};
+          } else if (nn == 0) {
+            v = {A[0].x, B[0].x};
+          }
+        }
+      }
+      buf[e * RPB + f] = v;
+    }
+    __syncthreads();
+    fft_lds<T, L, RPB, TPF, +1>(buf, W, t, f);
+    C2<T>* dstv = which == 0 ? hu : (which == 1 ? hw : g);
+#pragma unroll
+    for (int k = 0; k < PTS; ++k) dstv[k] = buf[(t + k * TPF) * RPB + f];
+    __syncthreads();
+  }
+  // products at the PTS points e = t + k TPF held by this thread
+  C2<T> hn[PTS];
+  T nz[PTS];
+#pragma unroll
+  for (int k = 0; k < PTS; ++k) {
+    const T uzv = g[k].x, wzv = g[k].y;
+    hn[k] = {uzv * hw[k].y - wzv * hu[k].y, wzv * hu[k].x - uzv * hw[k].x};
+    nz[k] = hw[k].x * hu[k].y - hw[k].y * hu[k].x;
+  }
+  // forward transform of N_r + i N_theta -> N+ (n >= 0) and conj(N-(-n))
+#pragma unroll
+  for (int k = 0; k < PTS; ++k) buf[(t + k * TPF) * RPB + f] = hn[k];
+  __syncthreads();
+  fft_lds<T, L, RPB, TPF, -1>(buf, W, t, f);
+  if (valid) {
+    C2<T>* Bp = base;
+    C2<T>* Bm = base + fstride;
+    for (int nn = t; nn < mt; nn += TPF) {
+      Bp[nn] = buf[nn * RPB + f];
+      Bm[nn] = cconj(buf[((L - nn) % L) * RPB + f]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PTS; ++k) buf[(t + k * TPF) * RPB + f] = C2<T>{nz[k], T(0)};
+  __syncthreads();
+  fft_lds<T, L, RPB, TPF, -1>(buf, W, t, f);
+  if (valid) {
+    C2<T>* Bz = base + 2 * fstride;
+    for (int nn = t; nn < mt; nn += TPF) Bz[nn] = buf[nn * RPB + f];
+  }
+}
+
+// ------------------------------------------------------------------ z forward
+template <typename T, int L>
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0,
+                                                                             const C2<T>* __restrict__ inter,
+                                                                             cd* __restrict__ N,
+                                                                             const C2<T>* __restrict__ W,
+                                                                             double scale) {
+  constexpr int NF = ZShape<T, L>::NF, TPF = ZShape<T, L>::TPF;
+  extern __shared__ unsigned char lds_raw[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+  const int tiles = (d.mt + NF - 1) / NF;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = bid % tiles;
+  const int rest = bid / tiles;
+  const int fld = rest % 3, pl = rest / 3;
+  const int f = threadIdx.x % NF, t = threadIdx.x / NF;
+  const int n = tile * NF + f;
+  const bool valid = n < d.mt;
+  const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt;
+  for (int e = t; e < L; e += TPF) buf[e * NF + f] = valid ? src[(int64_t)e * d.mt + n] : C2<T>{T(0), T(0)};
+  __syncthreads();
+  fft_lds<T, L, NF, TPF, -1>(buf, W, t, f);
+  if (!valid) return;
+  cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S;
+  const int h = d.half;
+  for (int s = t; s < d.mz; s += TPF) {
+    cd v = {0.0, 0.0};
+    if (s != h) {
+      const int e = s < h ? s : L - (d.mz - s);
+      const C2<T> x = buf[e * NF + f];
+      v = {double(x.x) * scale, double(x.y) * scale};
+    }
+    dst[(int64_t)s * d.mt + n] = v;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+#define TC_FFT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+bool fft_length_supported(int L) {
+#define TC_CASE(LL) if (L == LL) return true;
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return false;
+}
+
+size_t inter_bytes_per_plane(const tc_ctx* c) {
+  const size_t el = (c->g.precision == TC_FP32_BULK) ? sizeof(cf) : sizeof(cd);
+  return (size_t)6 * c->d.pz * c->d.mt * el;
+}
+
+template <typename T, int L>
+static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om, const C2<T>* W) {
+  using Z = ZShape<T, L>;
+  const size_t lds = (size_t)L * Z::NF * sizeof(C2<T>);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zinv<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr = true;
+  }
+  const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
+  const unsigned blocks = (unsigned)np * 6u * (unsigned)tiles;
+  hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, u, om,
+                     reinterpret_cast<C2<T>*>(c->inter), W);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t run_theta(tc_ctx* c, int np, const C2<T>* W) {
+  using TS = TShape<L>;
+  const size_t lds = (size_t)L * TS::RPB * sizeof(C2<T>);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_theta<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr = true;
+  }
+  const int64_t rows = (int64_t)np * c->d.pz;
+  const unsigned blocks = (unsigned)((rows + TS::RPB - 1) / TS::RPB);
+  hipLaunchKernelGGL((k_theta<T, L>), dim3(blocks), dim3(TS::TPF * TS::RPB), lds, c->stream, c->d, np,
+                     reinterpret_cast<C2<T>*>(c->inter), W);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, cd* N, const C2<T>* W) {
+  using Z = ZShape<T, L>;
+  const size_t lds = (size_t)L * Z::NF * sizeof(C2<T>);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zfwd<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr = true;
+  }
+  const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
+  const unsigned blocks = (unsigned)np * 3u * (unsigned)tiles;
+  const double scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
+  hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0,
+                     reinterpret_cast<const C2<T>*>(c->inter), N, W, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om) {
+  const bool f32 = c->g.precision == TC_FP32_BULK;
+#define TC_CASE(LL)                                                                   \
+  if (c->d.pz == LL) return f32 ? run_zinv<float, LL>(c, plane0, np, u, om, c->twf_z) \
+                                : run_zinv<double, LL>(c, plane0, np, u, om, c->tw_z);
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_theta(tc_ctx* c, int np) {
+  const bool f32 = c->g.precision == TC_FP32_BULK;
+#define TC_CASE(LL) \
+  if (c->d.pt == LL) return f32 ? run_theta<float, LL>(c, np, c->twf_t) : run_theta<double, LL>(c, np, c->tw_t);
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_zfwd(tc_ctx* c, int plane0, int np, cd* N) {
+  const bool f32 = c->g.precision == TC_FP32_BULK;
+#define TC_CASE(LL) \
+  if (c->d.pz == LL) return f32 ? run_zfwd<float, LL>(c, plane0, np, N, c->twf_z) : run_zfwd<double, LL>(c, plane0, np, N, c->tw_z);
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tc

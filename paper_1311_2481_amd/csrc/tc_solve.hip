@@ -1,0 +1,543 @@
+// Banded LU factorisation, banded solves and the fused predictor-corrector
+// step (Sec. 3.2, steps 2-5 of the paper; factors once, substitutions per
+// step as the paper's last paragraph of Sec. 3.2 prescribes).
+//
+// Work decomposition: one lane per distinct mode (|l|, n).  A lane serves
+// both axial slots +l and -l, whose operators are identical (they depend on
+// l^2 only), so every factor load is used twice.  Lanes of a wave hold
+// consecutive n, so every load and store of a radial row is one contiguous
+// run per slot in the [j][s][n] layout: no transposition is needed between
+// the transform layout and the solves.
+//
+// Factor layout and row order: see tc_internal.h.  The pressure operator P
+// is factored with rows taken in ascending order (LU), the three Helmholtz
+// operators in descending order (UL).  A solve with P therefore ends on a
+// descending sweep and a Helmholtz solve starts with one, so the
+// back-substitution of p* and the first sweep for u* share one pass over
+// the rows; likewise u*'s second sweep and phi's first sweep share the next
+// ascending pass.  The whole step is four passes over the radial rows.
+//
+// No pivoting: the Neumann rows of P are rescaled to the size of the
+// neighbouring Laplacian rows, and the factorisation reports any zero or
+// non-finite pivot.
+#include "tc_internal.h"
+
+namespace tc {
+
+__device__ __forceinline__ cd cz() { return cd{0.0, 0.0}; }
+__device__ __forceinline__ cd cfma(cd acc, double w, cd v) { return cd{fma(w, v.x, acc.x), fma(w, v.y, acc.y)}; }
+__device__ __forceinline__ cd cnfma(cd acc, double w, cd v) { return cd{fma(-w, v.x, acc.x), fma(-w, v.y, acc.y)}; }
+__device__ __forceinline__ cd cmuls(cd v, double w) { return cd{v.x * w, v.y * w}; }
+// i * w * v
+__device__ __forceinline__ cd cimul(cd v, double w) { return cd{-w * v.y, w * v.x}; }
+
+struct ModeLane {
+  int dm, labs, n;
+  int64_t o[2];  // plane offsets of slots +l and -l
+  double a, b[2];
+  bool zero_mode;
+};
+
+__device__ __forceinline__ bool make_lane(const Dims& d, ModeLane& L) {
+  L.dm = blockIdx.x * blockDim.x + threadIdx.x;
+  if (L.dm >= d.ndm) return false;
+  L.labs = L.dm / d.mt;
+  L.n = L.dm - L.labs * d.mt;
+  const int s1 = L.labs;
+  const int s2 = L.labs ? d.mz - L.labs : 0;
+  L.o[0] = (int64_t)s1 * d.mt + L.n;
+  L.o[1] = (int64_t)s2 * d.mt + L.n;
+  L.a = L.n * d.kt;
+  L.b[0] = L.labs * d.kz;
+  L.b[1] = -L.labs * d.kz;
+  L.zero_mode = (L.labs == 0 && L.n == 0);
+  return true;
+}
+
+__device__ __forceinline__ const double* facp(const double* fac, const Dims& d, int op, int j) {
+  return fac + ((int64_t)(op * d.n_r + j) * NFAC) * d.ndm;
+}
+
+// ------------------------------------------------------------------ factor
+// Row j of operator op in natural column order: entry k multiplies node j+k-4.
+__device__ void operator_row(const double* rc, const Dims& d, int op, int j, double a, double b, double* row) {
+  const double* R = rc + (int64_t)j * RC_N;
+  const int M = d.n_r - 1;
+  const bool wall = (j == 0 || j == M);
+  if (op == OP_P) {
+    if (wall) {
+      if (j == M && a == 0.0 && b == 0.0) {
+        for (int k = 0; k < NB9; ++k) row[k] = (k == HW) ? 1.0 : 0.0;
+      } else {
+        const double s = (j == 0) ? d.s0 : d.sM;
+        for (int k = 0; k < NB9; ++k) row[k] = s * R[RC_W1 + k];
+      }
+      return;
+    }
+  } else if (wall) {
+    for (int k = 0; k < NB9; ++k) row[k] = (k == HW) ? 1.0 : 0.0;
+    return;
+  }
+  for (int k = 0; k < NB9; ++k) row[k] = R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR];
+  double diag = -(a * a) * R[RC_IR2] - b * b;
+  if (op == OP_HP) diag += -(1.0 + 2.0 * a) * R[RC_IR2] - 1.5 / d.dt;
+  if (op == OP_HM) diag += -(1.0 - 2.0 * a) * R[RC_IR2] - 1.5 / d.dt;
+  if (op == OP_HZ) diag += -1.5 / d.dt;
+  row[HW] += diag;
+}
+
+__global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac, Dims d, int* bad) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= NOPS * d.ndm) return;
+  const int op = gid / d.ndm, dm = gid - op * d.ndm;
+  const int labs = dm / d.mt, n = dm - labs * d.mt;
+  const double a = n * d.kt, b = labs * d.kz;
+  const bool rev = (op != OP_P);
+  const int M = d.n_r - 1;
+  double U[4][5];  // U[q]: U-row of the row q+1 places earlier in processing order
+  for (int q = 0; q < 4; ++q)
+    for (int c = 0; c < 5; ++c) U[q][c] = 0.0;
+  int flag = 0;
+  for (int ip = 0; ip <= M; ++ip) {
+    const int j = rev ? M - ip : ip;
+    double nat[NB9], row[NB9];
+    operator_row(rc, d, op, j, a, b, nat);
+    for (int c = 0; c < NB9; ++c) row[c] = rev ? nat[NB9 - 1 - c] : nat[c];
+    double* F = const_cast<double*>(facp(fac, d, op, j)) + dm;
+    // eliminate the columns of the 4 previous rows, oldest first
+    for (int q = 4; q >= 1; --q) {
+      double m = 0.0;
+      if (ip - q >= 0) {
+        m = row[HW - q] / U[q - 1][0];
+        for (int c = 0; c < 5; ++c) row[HW - q + c] -= m * U[q - 1][c];
+      }
+      F[(int64_t)(q - 1) * d.ndm] = m;
+    }
+    const double piv = row[HW];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) flag = 1;
+    F[(int64_t)4 * d.ndm] = 1.0 / piv;
+    for (int c = 1; c <= 4; ++c) F[(int64_t)(4 + c) * d.ndm] = (ip + c <= M) ? row[HW + c] : 0.0;
+    for (int q = 3; q >= 1; --q)
+      for (int c = 0; c < 5; ++c) U[q][c] = U[q - 1][c];
+    for (int c = 0; c < 5; ++c) U[0][c] = row[HW + c];
+  }
+  if (flag) atomicOr(bad, 1);
+}
+
+hipError_t launch_factor(tc_ctx* c, int* bad_dev) {
+  const int total = NOPS * c->d.ndm;
+  hipLaunchKernelGGL(k_factor, dim3((total + 63) / 64), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, bad_dev);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ standalone solve
+// One operator, every mode.  The first sweep writes its intermediate into x,
+// the second sweep overwrites it with the solution (x may alias rhs).
+__global__ __launch_bounds__(64) void k_solve(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
+                                              int op, const cd* rhs, cd* x) {
+  ModeLane L;
+  if (!make_lane(d, L)) return;
+  const int M = d.n_r - 1;
+  const bool rev = (op != OP_P);
+  cd w[4][2];
+  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
+  for (int ip = 0; ip <= M; ++ip) {
+    const int j = rev ? M - ip : ip;
+    const double* F = facp(fac, d, op, j) + L.dm;
+    double scale = 1.0;
+    if (op == OP_P) scale = (j == 0) ? d.s0 : (j == M ? d.sM : 1.0);
+    if (op == OP_P && j == M && L.zero_mode) scale = 1.0;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      cd y = cmuls(rhs[j * d.S + L.o[m]], scale);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y = cnfma(y, F[(int64_t)q * d.ndm], w[q][m]);
+      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
+      w[0][m] = y;
+    }
+    x[j * d.S + L.o[0]] = w[0][0];
+    x[j * d.S + L.o[1]] = w[0][1];
+  }
+  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
+  for (int ip = M; ip >= 0; --ip) {
+    const int j = rev ? M - ip : ip;
+    const double* F = facp(fac, d, op, j) + L.dm;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      cd y = x[j * d.S + L.o[m]];
+#pragma unroll
+      for (int c = 1; c <= 4; ++c) y = cnfma(y, F[(int64_t)(4 + c) * d.ndm], w[c - 1][m]);
+      y = cmuls(y, F[(int64_t)4 * d.ndm]);
+      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
+      w[0][m] = y;
+    }
+    x[j * d.S + L.o[0]] = w[0][0];
+    x[j * d.S + L.o[1]] = w[0][1];
+  }
+}
+
+// Transposed solve A^T x = rhs with A = S^-1 L U (S: the Neumann row scale of
+// P, identity for the Helmholtz operators), in the factor's row order:
+// U^T w = rhs forwards, then L^T v = w backwards, then x = S v.
+__global__ __launch_bounds__(64) void k_solve_t(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
+                                                int op, const cd* rhs, cd* x) {
+  ModeLane L;
+  if (!make_lane(d, L)) return;
+  const int M = d.n_r - 1;
+  const bool rev = (op != OP_P);
+  auto row_of = [&](int ip) { return rev ? M - ip : ip; };
+  cd w[4][2];
+  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
+  for (int ip = 0; ip <= M; ++ip) {
+    const int j = row_of(ip);
+    const double inv = facp(fac, d, op, j)[(int64_t)4 * d.ndm + L.dm];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      cd y = rhs[j * d.S + L.o[m]];
+#pragma unroll
+      for (int c = 1; c <= 4; ++c) {
+        if (ip - c >= 0) {
+          const double u = facp(fac, d, op, row_of(ip - c))[(int64_t)(4 + c) * d.ndm + L.dm];
+          y = cnfma(y, u, w[c - 1][m]);
+        }
+      }
+      y = cmuls(y, inv);
+      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
+      w[0][m] = y;
+    }
+    x[j * d.S + L.o[0]] = w[0][0];
+    x[j * d.S + L.o[1]] = w[0][1];
+  }
+  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
+  for (int ip = M; ip >= 0; --ip) {
+    const int j = row_of(ip);
+    double scale = 1.0;
+    if (op == OP_P) scale = (j == 0) ? d.s0 : (j == M ? d.sM : 1.0);
+    if (op == OP_P && j == M && L.zero_mode) scale = 1.0;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      cd y = x[j * d.S + L.o[m]];
+#pragma unroll
+      for (int q = 1; q <= 4; ++q) {
+        if (ip + q <= M) {
+          const double mult = facp(fac, d, op, row_of(ip + q))[(int64_t)(q - 1) * d.ndm + L.dm];
+          y = cnfma(y, mult, w[q - 1][m]);
+        }
+      }
+      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
+      w[0][m] = y;
+    }
+    x[j * d.S + L.o[0]] = cmuls(w[0][0], scale);
+    x[j * d.S + L.o[1]] = cmuls(w[0][1], scale);
+  }
+}
+
+hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x) {
+  const int blocks = (c->d.ndm + 63) / 64;
+  if (transposed)
+    hipLaunchKernelGGL(k_solve_t, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, op, rhs, x);
+  else
+    hipLaunchKernelGGL(k_solve, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, op, rhs, x);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fused predictor-corrector
+// V_r(u) at a wall row: 1/2 (L+ u+ + L- u-), L+- = D2 + D1/r - (a^2+1+-2a)/r^2 - b^2.
+__device__ __forceinline__ cd wall_vr(const double* R, double a, double b, const cd* vp, const cd* vm, int kbeg) {
+  // vp/vm hold u+-/u- at nodes j+k-4 for k = kbeg..kbeg+4 (index k - kbeg)
+  cd acc = cz();
+  for (int t = 0; t < 5; ++t) {
+    const int k = kbeg + t;
+    const double w = R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR];
+    acc = cfma(acc, 0.5 * w, cadd(vp[t], vm[t]));
+  }
+  const int t0 = HW - kbeg;  // index of the row itself
+  const double dsum = -(a * a + 1.0) * R[RC_IR2] - b * b;
+  acc = cfma(acc, 0.5 * dsum, cadd(vp[t0], vm[t0]));
+  acc = cfma(acc, -a * R[RC_IR2], csub(vp[t0], vm[t0]));
+  return acc;
+}
+
+// Sweeps (rows j = 0..M):
+//  1 ascending : RHS of the pressure Poisson problem, forward sweep of P  -> y_p   (in p)
+//  2 descending: p* by back-substitution; RHS of the 3 Helmholtz problems;
+//                first (descending) sweep of H+, H-, H_z                 -> z     (in u_next), p* (in p)
+//  3 ascending : u* by the second sweep; RHS of phi; forward sweep of P  -> u* (in u_next), y_phi (in N_prev[0])
+//  4 descending: phi by back-substitution; correction and pressure update -> u^{i+1} (in u_next), p
+// Stencil terms lag the sweep by 4 rows (the D1 stencil spans +-4 rows).
+__global__ __launch_bounds__(64) void k_pc(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
+                                           const cd* __restrict__ u, const cd* up, const cd* __restrict__ N,
+                                           cd* Np, cd* un, cd* p) {
+  ModeLane L;
+  if (!make_lane(d, L)) return;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const double a = L.a;
+  // |l| = 0 has a single slot: its second "mode" would alias the first
+  // (read-modify-write of the same words), so it is skipped throughout.
+  const bool two = L.labs != 0;
+  const double c_dt = 1.0 / (2.0 * d.dt);
+
+  // ---- wall rows of the consistent Neumann condition: 2 V_r(u^i) - V_r(u^{i-1})
+  cd bc[2][2];  // [wall][mode]
+  for (int wsel = 0; wsel < 2; ++wsel) {
+    const int j = wsel ? M : 0;
+    const int kbeg = wsel ? 0 : HW;
+    const double* R = rc + (int64_t)j * RC_N;
+    for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+      cd vp[5], vm[5], wp[5], wm[5];
+      for (int t = 0; t < 5; ++t) {
+        const int node = j + kbeg + t - HW;
+        const int64_t o = node * S + L.o[m];
+        vp[t] = u[o]; vm[t] = u[F + o];
+        wp[t] = up[o]; wm[t] = up[F + o];
+      }
+      const cd v1 = wall_vr(R, a, L.b[m], vp, vm, kbeg);
+      const cd v0 = wall_vr(R, a, L.b[m], wp, wm, kbeg);
+      bc[wsel][m] = cd{2.0 * v1.x - v0.x, 2.0 * v1.y - v0.y};
+    }
+  }
+
+  // ---- sweep 1 (ascending)
+  {
+    cd win[NB9][2], loc[5][2], yw[4][2];
+    for (int k = 0; k < NB9; ++k) win[k][0] = win[k][1] = cz();
+    for (int k = 0; k < 5; ++k) loc[k][0] = loc[k][1] = cz();
+    for (int q = 0; q < 4; ++q) yw[q][0] = yw[q][1] = cz();
+    for (int j = 0; j <= M + HW; ++j) {
+      for (int k = 0; k < NB9 - 1; ++k) { win[k][0] = win[k + 1][0]; win[k][1] = win[k + 1][1]; }
+      for (int k = 0; k < 4; ++k) { loc[k][0] = loc[k + 1][0]; loc[k][1] = loc[k + 1][1]; }
+      if (j <= M) {
+        const double ir = rc[(int64_t)j * RC_N + RC_IR];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+          const int64_t o = j * S + L.o[m];
+          const cd ep = csub(cmuls(N[o], 2.0), Np[o]);
+          const cd em = csub(cmuls(N[F + o], 2.0), Np[F + o]);
+          const cd ez = csub(cmuls(N[2 * F + o], 2.0), Np[2 * F + o]);
+          const cd er = cmuls(cadd(ep, em), 0.5);
+          win[NB9 - 1][m] = er;
+          cd l = cmuls(er, ir);
+          l = cfma(l, 0.5 * a * ir, csub(ep, em));
+          l = cadd(l, cimul(ez, L.b[m]));
+          loc[4][m] = l;
+        }
+      } else {
+        win[NB9 - 1][0] = win[NB9 - 1][1] = cz();
+      }
+      const int i = j - HW;
+      if (i < 0) continue;
+      const double* R = rc + (int64_t)i * RC_N;
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+        cd rhs;
+        if (i == 0) {
+          rhs = cmuls(csub(bc[0][m], win[HW][m]), d.s0);
+        } else if (i == M) {
+          rhs = L.zero_mode ? cz() : cmuls(csub(bc[1][m], win[HW][m]), d.sM);
+        } else {
+          cd dd = loc[0][m];
+#pragma unroll
+          for (int k = 0; k < NB9; ++k) dd = cfma(dd, R[RC_W1 + k], win[k][m]);
+          rhs = cd{-dd.x, -dd.y};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yw[q][m]);
+        for (int q = 3; q >= 1; --q) yw[q][m] = yw[q - 1][m];
+        yw[0][m] = rhs;
+        p[i * S + L.o[m]] = rhs;
+      }
+    }
+  }
+
+  // ---- sweep 2 (descending)
+  {
+    cd pw[NB9][2], zw[3][4][2];
+    for (int k = 0; k < NB9; ++k) pw[k][0] = pw[k][1] = cz();
+    for (int o = 0; o < 3; ++o)
+      for (int q = 0; q < 4; ++q) zw[o][q][0] = zw[o][q][1] = cz();
+    for (int jj = M; jj >= -HW; --jj) {
+      for (int k = NB9 - 1; k >= 1; --k) { pw[k][0] = pw[k - 1][0]; pw[k][1] = pw[k - 1][1]; }
+      if (jj >= 0) {
+        const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
+        const double inv = Fp[(int64_t)4 * d.ndm];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+          cd y = p[jj * S + L.o[m]];
+#pragma unroll
+          for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], pw[c][m]);
+          y = cmuls(y, inv);
+          pw[0][m] = y;
+          p[jj * S + L.o[m]] = y;
+        }
+      } else {
+        pw[0][0] = pw[0][1] = cz();
+      }
+      const int i = jj + HW;
+      if (i > M) continue;
+      const double* R = rc + (int64_t)i * RC_N;
+      const double ir = R[RC_IR];
+      const bool wall = (i == 0 || i == M);
+      const double Re = (i == 0) ? d.Re_i : d.Re_o;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+        cd rhs[3];
+        if (wall) {
+          rhs[0] = L.zero_mode ? cd{0.0, Re} : cz();
+          rhs[1] = L.zero_mode ? cd{0.0, -Re} : cz();
+          rhs[2] = cz();
+        } else {
+          cd d1 = cz();
+#pragma unroll
+          for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], pw[k][m]);
+          const cd pi = pw[HW][m];
+          const int64_t o = i * S + L.o[m];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cd ne = csub(cmuls(N[c * F + o], 2.0), Np[c * F + o]);
+            const cd ut = csub(cmuls(u[c * F + o], 4.0), up[c * F + o]);
+            cd r = cd{ne.x - ut.x * c_dt, ne.y - ut.y * c_dt};
+            if (c == 0) r = cadd(r, cnfma(d1, a * ir, pi));
+            if (c == 1) r = cadd(r, cfma(d1, a * ir, pi));
+            if (c == 2) r = cadd(r, cimul(pi, L.b[m]));
+            rhs[c] = r;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
+          cd z = rhs[c];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) z = cnfma(z, Fh[(int64_t)q * d.ndm], zw[c][q][m]);
+          for (int q = 3; q >= 1; --q) zw[c][q][m] = zw[c][q - 1][m];
+          zw[c][0][m] = z;
+          un[c * F + i * S + L.o[m]] = z;
+        }
+      }
+    }
+  }
+
+  // ---- sweep 3 (ascending)
+  {
+    cd xw[3][4][2], rw[NB9][2], lf[5][2], yp[4][2];
+    for (int c = 0; c < 3; ++c)
+      for (int q = 0; q < 4; ++q) xw[c][q][0] = xw[c][q][1] = cz();
+    for (int k = 0; k < NB9; ++k) rw[k][0] = rw[k][1] = cz();
+    for (int k = 0; k < 5; ++k) lf[k][0] = lf[k][1] = cz();
+    for (int q = 0; q < 4; ++q) yp[q][0] = yp[q][1] = cz();
+    for (int j = 0; j <= M + HW; ++j) {
+      for (int k = 0; k < NB9 - 1; ++k) { rw[k][0] = rw[k + 1][0]; rw[k][1] = rw[k + 1][1]; }
+      for (int k = 0; k < 4; ++k) { lf[k][0] = lf[k + 1][0]; lf[k][1] = lf[k + 1][1]; }
+      if (j <= M) {
+        const double ir = rc[(int64_t)j * RC_N + RC_IR];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+          cd xs[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double* Fh = facp(fac, d, OP_HP + c, j) + L.dm;
+            const int64_t o = c * F + j * S + L.o[m];
+            cd y = un[o];
+#pragma unroll
+            for (int q = 1; q <= 4; ++q) y = cnfma(y, Fh[(int64_t)(4 + q) * d.ndm], xw[c][q - 1][m]);
+            y = cmuls(y, Fh[(int64_t)4 * d.ndm]);
+            for (int q = 3; q >= 1; --q) xw[c][q][m] = xw[c][q - 1][m];
+            xw[c][0][m] = y;
+            un[o] = y;
+            xs[c] = y;
+          }
+          const cd ur = cmuls(cadd(xs[0], xs[1]), 0.5);
+          rw[NB9 - 1][m] = ur;
+          cd l = cmuls(ur, ir);
+          l = cfma(l, 0.5 * a * ir, csub(xs[0], xs[1]));
+          l = cadd(l, cimul(xs[2], L.b[m]));
+          lf[4][m] = l;
+        }
+      } else {
+        rw[NB9 - 1][0] = rw[NB9 - 1][1] = cz();
+      }
+      const int i = j - HW;
+      if (i < 0) continue;
+      const double* R = rc + (int64_t)i * RC_N;
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+        cd rhs = cz();
+        if (i != 0 && i != M) {
+          rhs = lf[0][m];
+#pragma unroll
+          for (int k = 0; k < NB9; ++k) rhs = cfma(rhs, R[RC_W1 + k], rw[k][m]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yp[q][m]);
+        for (int q = 3; q >= 1; --q) yp[q][m] = yp[q - 1][m];
+        yp[0][m] = rhs;
+        Np[i * S + L.o[m]] = rhs;
+      }
+    }
+  }
+
+  // ---- sweep 4 (descending)
+  {
+    cd fw[NB9][2];
+    for (int k = 0; k < NB9; ++k) fw[k][0] = fw[k][1] = cz();
+    const double c_p = 1.5 / d.dt;
+    for (int jj = M; jj >= -HW; --jj) {
+      for (int k = NB9 - 1; k >= 1; --k) { fw[k][0] = fw[k - 1][0]; fw[k][1] = fw[k - 1][1]; }
+      if (jj >= 0) {
+        const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
+        const double inv = Fp[(int64_t)4 * d.ndm];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+          cd y = Np[jj * S + L.o[m]];
+#pragma unroll
+          for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], fw[c][m]);
+          fw[0][m] = cmuls(y, inv);
+        }
+      } else {
+        fw[0][0] = fw[0][1] = cz();
+      }
+      const int i = jj + HW;
+      if (i > M) continue;
+      const double* R = rc + (int64_t)i * RC_N;
+      const double ir = R[RC_IR];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) continue;
+        cd d1 = cz();
+#pragma unroll
+        for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k][m]);
+        const cd ph = fw[HW][m];
+        const int64_t o = i * S + L.o[m];
+        const cd gpl = cnfma(d1, a * ir, ph);
+        const cd gmi = cfma(d1, a * ir, ph);
+        un[o] = csub(un[o], gpl);
+        un[F + o] = csub(un[F + o], gmi);
+        un[2 * F + o] = csub(un[2 * F + o], cimul(ph, L.b[m]));
+        p[o] = cfma(p[o], c_p, ph);
+      }
+      if (L.labs == 0) {
+        const int64_t o = i * S + (int64_t)d.nyq * d.mt + L.n;
+        un[o] = cz(); un[F + o] = cz(); un[2 * F + o] = cz(); p[o] = cz();
+      }
+    }
+  }
+}
+
+hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p) {
+  const int blocks = (c->d.ndm + 63) / 64;
+  hipLaunchKernelGGL(k_pc, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, u, u_prev, N, N_prev,
+                     u_next, p);
+  return hipGetLastError();
+}
+
+}  // namespace tc
