@@ -1,0 +1,214 @@
+"""Throughput of the Taylor-Couette projection step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload production]
+
+One step = the whole hot path (pseudospectral nonlinear term with 3/2
+dealiasing + fused pressure/velocity/correction solves) on a synthetic
+perturbed-Couette state already resident in HBM.  Prints ONE JSON line.
+Per-kernel launch times come from HIP events recorded by the library on the
+stream its kernels run on.  The CPU baseline times the FP64 oracle on a
+bounded sample of the same workload and extrapolates (planes and modes are
+independent).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time steps/s & grid-pt updates/s (FP64 vs FP32-bulk); adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload_label(cfg, name):
+    return (f"{name}: eta={cfg.eta}, Re_i={cfg.Re_i:g}, Re_o={cfg.Re_o:.6g}, N_r={cfg.n_r}, "
+            f"{2 * cfg.m_theta}x{cfg.m_z} physical (theta,z), {3 * cfg.m_theta}x{3 * cfg.m_z // 2} dealiased, "
+            f"dt={cfg.dt:g}, perturbation amp {cfg.amp:g} ({cfg.envelope}), seed {cfg.seed}")
+
+
+def kernel_bytes(cfg, precision):
+    """Algorithmic bytes per launch of each kernel (one full step, all planes)."""
+    n_r, mt, mz = cfg.n_r, cfg.m_theta, cfg.m_z
+    pz = 3 * mz // 2
+    ndm = mt * (mz // 2)
+    modes = mt * (mz - 1)             # stored modes without the empty slot
+    el = 8 if precision == "fp32_bulk" else 16
+    inter = pz * mt * el               # one field of one plane, transform layout
+    spec = modes * 16                  # one spectral field of one plane
+    return {
+        # in: u^i, u^{i-1}, N^i, N^{i-1} (12 fields); out: u^{i+1}, p (4 fields);
+        # LU factors of 4 operators, 9 doubles per row, shared by +-l
+        "pc": 16 * 16 * n_r * modes + 4 * 9 * 8 * n_r * ndm,
+        "curl": 6 * spec * n_r,
+        "zinv": (6 * spec + 6 * inter) * n_r,
+        "theta": 9 * inter * n_r,
+        "zfwd": (3 * inter + 3 * spec) * n_r,
+    }
+
+
+def read_traffic(kernel, workload, precision):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1311_2481_amd", "csrc", vals.get("source", ""))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != vals.get("source_sha"):
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(cfg, precision, steps, warmup, u0):
+    import torch
+    from paper_1311_2481_amd import Solver, KERNELS
+    S = Solver(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
+               k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha, precision=precision)
+    S.set_state(u0)
+    S.step(warmup)
+    torch.cuda.synchronize()
+    S.set_timing(True)
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = {k: S.kernel_time(k) for k in KERNELS}
+    S.set_timing(False)
+    finite = S.check_finite()
+    diag = S.diag()
+    mem = S.memory_bytes()
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    return dict(seconds=dt, times=times, finite=finite, diag=diag, mem=mem)
+
+
+def cpu_baseline(cfg, u0_dev, repeats=3):
+    """FP64 oracle on a bounded sample: 9 full-size radial planes of the
+    nonlinear term and the predictor-corrector for the l = 0, +-1 modes at
+    full radial resolution; extrapolated linearly to one whole step."""
+    import torch
+    import oracle
+    from oracle import scheme
+    from oracle.nonlinear import WORKERS
+    n_r, mt, mz = cfg.n_r, cfg.m_theta, cfg.m_z
+    # nonlinear: 9 consecutive planes, full (theta, z) size
+    k = 9
+    Pn = oracle.Problem(k, mt, mz, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+    slab = u0_dev[:, :k].cpu().numpy()
+    oracle.nonlinear_rot(Pn, slab)  # warm-up
+    tn = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.nonlinear_rot(Pn, slab)
+        tn.append(time.perf_counter() - t0)
+    per_plane = float(np.median(tn)) / k
+    # predictor-corrector: slots l = 0, +-1 of every n at full radial size
+    Pm = oracle.Problem(n_r, mt, 4, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+    idx = torch.tensor([0, 1, mz - 1], device=u0_dev.device)
+    sub = np.zeros((3, n_r, 4, mt), dtype=np.complex128)
+    sel = u0_dev.index_select(2, idx).cpu().numpy()
+    sub[:, :, [0, 1, 3]] = sel
+    N = sub.copy()  # stand-in nonlinear terms: the values do not change the cost
+    scheme.predictor_corrector(Pm, N, N, sub, sub)  # factorisation happens here (set-up)
+    tm = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        scheme.predictor_corrector(Pm, N, 0.5 * N, sub, 0.9 * sub)
+        tm.append(time.perf_counter() - t0)
+    nmodes_sample = 3 * mt
+    per_mode = float(np.median(tm)) / nmodes_sample
+    t_step = per_plane * n_r + per_mode * (mz - 1) * mt
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": WORKERS, "kind": "oracle",
+            "sample": (f"{k} full-size radial planes of the nonlinear term ({per_plane:.3f} s/plane) and the "
+                       f"predictor-corrector of {nmodes_sample} modes at n_r={n_r} ({per_mode * 1e3:.3f} ms/mode), "
+                       f"median of {repeats}; extrapolated to {n_r} planes and {(mz - 1) * mt} modes: "
+                       f"{t_step:.1f} s/step (scipy.fft with {WORKERS} workers, NumPy elementwise on 1 core)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="production")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import tc_inputs
+    from paper_1311_2481_amd import Solver
+
+    cfg = tc_inputs.Config(tc_inputs.CONFIGS[args.workload])
+    print(f"[bench] workload {args.workload}: building the initial state on the GPU", file=sys.stderr, flush=True)
+    # nodes from the library itself (no oracle on the product path)
+    probe = Solver(cfg.n_r, 16, 32, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
+                   k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha)
+    r = probe.radial_nodes()
+    probe.close()
+    u0 = tc_inputs.initial_state(r, cfg, device="cuda")
+    torch.cuda.synchronize()
+
+    print("[bench] FP64 step", file=sys.stderr, flush=True)
+    f64 = run_gpu(cfg, "fp64", args.steps, args.warmup, u0)
+    f32 = None
+    if not args.no_fp32:
+        print("[bench] FP32-bulk step", file=sys.stderr, flush=True)
+        f32 = run_gpu(cfg, "fp32_bulk", args.steps, args.warmup, u0)
+
+    pts = cfg.n_r * 2 * cfg.m_theta * cfg.m_z
+    sps = args.steps / f64["seconds"]
+    kb = kernel_bytes(cfg, "fp64")
+    per_step = {k: v[0] * max(v[1], 1) / args.steps for k, v in f64["times"].items()}
+    dom = max(per_step, key=per_step.get)
+    ms, nl = f64["times"][dom]
+    launches_per_step = nl / args.steps
+    alg = kb[dom] / launches_per_step
+    achieved = alg / (ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, args.workload, "fp64"),
+            "algorithmic_bytes_per_launch": int(alg), "mean_launch_ms": round(ms, 4)}
+    out = {
+        "metric": METRIC, "value": round(sps, 4), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 / sps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload_label(cfg, args.workload), "grid_points_per_step": pts},
+        "grid_pt_updates_per_s": round(sps * pts, 1),
+        "finite_after_run": f64["finite"],
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
+        "roofline": roof,
+    }
+    if f32:
+        s32 = args.steps / f32["seconds"]
+        out["fp32_bulk"] = {"value": round(s32, 4), "unit": "steps/s", "grid_pt_updates_per_s": round(s32 * pts, 1),
+                            "ms_per_step": round(1e3 / s32, 3), "speedup_vs_fp64": round(s32 / sps, 3),
+                            "finite_after_run": f32["finite"],
+                            "kernels_ms_per_step": {k: round(v[0] * max(v[1], 1) / args.steps, 4)
+                                                    for k, v in f32["times"].items()}}
+    out["adjoint_forward_ratio"] = None
+    if not args.no_cpu:
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, u0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

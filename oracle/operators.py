@@ -145,12 +145,22 @@ class Problem:
         return x
 
     # ------------------------------------------------------------------ radial helpers
+    def _band_apply(self, A, f):
+        """Apply a banded (kl = ku = 4) radial matrix along axis -3 of f."""
+        n = self.n_r
+        out = np.zeros(np.broadcast_shapes(f.shape), dtype=np.result_type(f, A))
+        for off in range(-HALF, HALF + 1):
+            rows = np.arange(max(0, -off), min(n, n - off))
+            coef = A[rows, rows + off]
+            out[..., rows, :, :] += coef[:, None, None] * f[..., rows + off, :, :]
+        return out
+
     def ddr(self, f):
         """Apply D1 along the radial axis of a (..., n_r, m_z, m_theta) array."""
-        return np.moveaxis(np.tensordot(self.D1, f, axes=(1, -3)), 0, -3)
+        return self._band_apply(self.D1, f)
 
     def ddr2(self, f):
-        return np.moveaxis(np.tensordot(self.D2, f, axes=(1, -3)), 0, -3)
+        return self._band_apply(self.D2, f)
 
     def bcast(self):
         """a, b and r broadcast against a (n_r, m_z, m_theta) array."""

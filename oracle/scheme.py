@@ -86,10 +86,8 @@ def correction_rhs(prob, u_star):
     return zero_nyquist(prob, rhs)
 
 
-def step(prob, u, u_prev, N_prev, N=None, detail=False):
-    """One projection step.  Returns (u_next, p_next, N) (+ intermediates if detail)."""
-    if N is None:
-        N = nonlinear_rot(prob, u)
+def predictor_corrector(prob, N, N_prev, u, u_prev, detail=False):
+    """Steps 2-5 for given N^i: returns (u^{i+1}, p^{i+1})."""
     Ne = 2.0 * N - N_prev
     rhs_p = pressure_rhs(prob, Ne, u, u_prev)
     p_star = prob.solve("P", rhs_p)
@@ -100,8 +98,18 @@ def step(prob, u, u_prev, N_prev, N=None, detail=False):
     p_next = zero_nyquist(prob, p_star + 1.5 * phi / prob.dt)
     u_next = zero_nyquist(prob, u_star - grad(prob, phi))
     if detail:
-        return u_next, p_next, N, dict(p_star=p_star, u_star=u_star, phi=phi, rhs_phi=rhs_phi)
-    return u_next, p_next, N
+        return u_next, p_next, dict(p_star=p_star, u_star=u_star, phi=phi, rhs_phi=rhs_phi)
+    return u_next, p_next
+
+
+def step(prob, u, u_prev, N_prev, N=None, detail=False):
+    """One projection step.  Returns (u_next, p_next, N) (+ intermediates if detail)."""
+    if N is None:
+        N = nonlinear_rot(prob, u)
+    out = predictor_corrector(prob, N, N_prev, u, u_prev, detail=detail)
+    if detail:
+        return out[0], out[1], N, out[2]
+    return out[0], out[1], N
 
 
 def run(prob, u0, nsteps, u_prev=None, N_prev=None):

@@ -98,8 +98,10 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
 // ------------------------------------------------------------------ launch shapes
 // z kernels: NF columns per workgroup, TPF threads per column (NF * TPF threads).
 template <typename T, int L> struct ZShape {
-  static constexpr int TPF = L >= 512 ? 64 : (L >= 128 ? 32 : 8);
-  static constexpr int LDS_CAP = 98304;  // bytes of LDS a workgroup may take
+  static constexpr int TPF = L >= 512 ? (sizeof(T) == 8 ? 128 : 64) : (L >= 128 ? 32 : 8);
+  // at most 48 KB of LDS per workgroup, so that three workgroups share a CU
+  // and one's transform overlaps another's loads and stores
+  static constexpr int LDS_CAP = 49152;
   static constexpr int NF0 = 256 / TPF;
   static constexpr int NF1 = LDS_CAP / (L * (int)sizeof(C2<T>));
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
@@ -159,9 +161,6 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
 }
 
 // ------------------------------------------------------------------ theta pass
-template <typename T>
-__device__ __forceinline__ C2<T> ld_inter(const C2<T>* row, int n) { return row[n]; }
-
 template <typename T, int L>
 __global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter,
                                                                           const C2<T>* __restrict__ W) {
@@ -178,8 +177,10 @@ __global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dim
   C2<T>* base = inter + (int64_t)pl * 6 * fstride + (int64_t)z * d.mt;
   const int mt = d.mt;
 
-  C2<T> hu[PTS], hw[PTS], g[PTS];
-  for (int which = 0; which < 3; ++which) {
+  // which = 0: h_u from (u+, u-); 1: h_omega from (omega+, omega-);
+  // 2: g = u_z + i omega_z.  Each: assemble the +-n spectrum, inverse
+  // transform, keep this thread's PTS points in registers.
+  auto inverse = [&](int which, C2<T>* out) {
     const C2<T>* A = base + (int64_t)(which == 0 ? 0 : (which == 1 ? 3 : 2)) * fstride;
     const C2<T>* B = base + (int64_t)(which == 0 ? 1 : (which == 1 ? 4 : 5)) * fstride;
     for (int e = t; e < L; e += TPF) {
@@ -194,7 +195,6 @@ __global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dim
             v = {T(0.5) * (p0.x + m0.x), T(0.5) * (p0.y - m0.y)};
           }
         } else {
-          // g = u_z + i omega_z; A = u_z column, B = omega_z column
           if (nn > 0 && nn < mt) {
             const C2<T> x = A[nn], y = B[nn];
             v = {x.x - y.y, x.y + y.x};
@@ -210,11 +210,14 @@ __global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dim
     }
     __syncthreads();
     fft_lds<T, L, RPB, TPF, +1>(buf, W, t, f);
-    C2<T>* dstv = which == 0 ? hu : (which == 1 ? hw : g);
 #pragma unroll
-    for (int k = 0; k < PTS; ++k) dstv[k] = buf[(t + k * TPF) * RPB + f];
+    for (int k = 0; k < PTS; ++k) out[k] = buf[(t + k * TPF) * RPB + f];
     __syncthreads();
-  }
+  };
+  C2<T> hu[PTS], hw[PTS], g[PTS];
+  inverse(0, hu);
+  inverse(1, hw);
+  inverse(2, g);
   // products at the PTS points e = t + k TPF held by this thread
   C2<T> hn[PTS];
   T nz[PTS];
