@@ -508,7 +508,7 @@ tc_status tc_step(tc_ctx* c, int32_t nsteps) {
     tc_status s = nonlinear(c, c->u, c->N_cur);
     if (s != TC_OK) return s;
     timer_begin(c, TK_PC);
-    hipError_t e = launch_pc(c, c->u, c->u_prev, c->N_cur, c->N_prev, c->u_prev, c->p);
+    hipError_t e = launch_pc(c, c->u, c->u_prev, c->N_cur, c->N_prev, c->u_prev, c->p, k == nsteps - 1);
     timer_end(c, TK_PC);
     if (e != hipSuccess) return hip_check(c, e, "predictor-corrector");
     std::swap(c->u, c->u_prev);

@@ -1,18 +1,29 @@
-// LDS-resident mixed-radix Stockham FFT for gfx950 (radices 8, 4, 2, 3, 5).
+// Mixed-radix Stockham FFT for gfx950 (radices 8, 4, 2, 3, 5), registers
+// plus LDS exchanges.
 //
-// A workgroup transforms NF sequences of length L at once.  Element e of
-// sequence f lives at buf[e * NF + f] in LDS, so the NF threads that handle
-// the same element of neighbouring sequences touch neighbouring addresses.
-// Each sequence is served by TPF threads; thread (t, f) has t in [0, TPF).
+// A workgroup transforms NF sequences of length L at once, TPF threads per
+// sequence; thread (t, f) has t in [0, TPF), f in [0, NF).
 //
 // Pass with radix R after the radices already applied (their product NS):
 // butterfly j in [0, L/R) reads x[j + q L/R], q = 0..R-1, multiplies input q
 // by w^(q k L/(NS R)) with k = j mod NS and w = exp(SIGN 2 pi i / L), takes
 // the R-point DFT and writes output s to (j / NS) NS R + k + s NS.  After
-// the last pass the data is in natural order (Stockham autosort).  Every
-// pass stages its inputs in registers between two barriers, so it runs in
-// place.  SIGN = +1 is the unnormalised inverse transform of eq. fourier,
-// SIGN = -1 the forward one (scaling is left to the caller).
+// the last pass the data is in natural order (Stockham autosort).
+// Butterfly j of every pass belongs to thread t = j mod TPF.
+//
+// The first pass takes its inputs from registers filled by the caller
+// (element j + q L/R0 in slot [k][q], j = t + k TPF), the last pass leaves
+// its outputs in registers (element j + s L/RN in slot [k][s]): only the
+// exchanges between passes go through LDS.  A transform run with the radix
+// order reversed starts exactly where a transform in natural order ends
+// (its first-pass inputs are the other's last-pass outputs in the same
+// slots), so a pointwise product between an inverse and a forward
+// transform never leaves registers.
+//
+// LDS layout: element e of sequence f at (e + e/8) * NF + f; the pad word
+// every 8 elements spreads the stride-8 writes of the early passes over
+// the banks.  SIGN = +1 is the unnormalised inverse transform of eq.
+// fourier, SIGN = -1 the forward one (scaling is left to the caller).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -122,60 +133,139 @@ template <int SIGN, typename T> struct Butterfly<5, SIGN, T> {
   }
 };
 
-// One Stockham pass.  W[e] = exp(-2 pi i e / L) (forward roots).
-template <typename T, int L, int NF, int TPF, int SIGN, int R, int NS>
-__device__ __forceinline__ void stockham_pass(C2<T>* buf, const C2<T>* __restrict__ W, int t, int f) {
-  constexpr int NB = L / R;
-  constexpr int PER = (NB + TPF - 1) / TPF;
-  C2<T> v[PER][R];
+
+constexpr RadixList reversed(RadixList rl) {
+  RadixList o{rl.n, {}};
+  for (int i = 0; i < rl.n; ++i) o.r[i] = rl.r[rl.n - 1 - i];
+  return o;
+}
+
+__host__ __device__ constexpr int lds_pad(int e) { return e + (e >> 3); }
+template <int L> __host__ __device__ constexpr int lds_len() { return lds_pad(L - 1) + 1; }
+
+template <typename T, int L, int TPF, int SIGN, bool REV>
+struct Fft {
+  static constexpr RadixList RL = REV ? reversed(make_radices(L)) : make_radices(L);
+  static_assert(RL.n > 0, "unsupported transform length");
+  static constexpr int P = RL.n;
+  static constexpr int R0 = RL.r[0];
+  static constexpr int RN = RL.r[P - 1];
+  static constexpr int PER0 = (L / R0 + TPF - 1) / TPF;
+  static constexpr int PERN = (L / RN + TPF - 1) / TPF;
+  using In = C2<T>[PER0][R0];
+  using Out = C2<T>[PERN][RN];
+
+  // middle pass P0 (0 < P0 < P-1): LDS src -> LDS dst
+  template <int NF, int PP>
+  static __device__ __forceinline__ void mid(const C2<T>* src, C2<T>* dst, const C2<T>* __restrict__ W, int t, int f,
+                                             bool inplace) {
+    constexpr int R = RL.r[PP];
+    constexpr int NS = radix_product(RL, PP);
+    constexpr int NB = L / R;
+    constexpr int PER = (NB + TPF - 1) / TPF;
+    C2<T> v[PER][R];
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int j = t + p * TPF;
-    if (NB % TPF == 0 || j < NB) {
+    for (int k = 0; k < PER; ++k) {
+      const int j = t + k * TPF;
+      if (NB % TPF == 0 || j < NB) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[p][q] = buf[(j + q * NB) * NF + f];
+        for (int q = 0; q < R; ++q) v[k][q] = src[lds_pad(j + q * NB) * NF + f];
+      }
     }
-  }
-  __syncthreads();
+    if (inplace) __syncthreads();
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int j = t + p * TPF;
-    if (NB % TPF == 0 || j < NB) {
-      const int k = j % NS;
-      if (NS > 1) {
+    for (int k = 0; k < PER; ++k) {
+      const int j = t + k * TPF;
+      if (NB % TPF == 0 || j < NB) {
+        const int kk = j % NS;
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          C2<T> w = W[(q * k * (L / (NS * R))) % L];
+          C2<T> w = W[(q * kk * (L / (NS * R))) % L];
           if (SIGN > 0) w.y = -w.y;
-          v[p][q] = cmul(v[p][q], w);
+          v[k][q] = cmul(v[k][q], w);
         }
-      }
-      Butterfly<R, SIGN, T>::run(v[p]);
-      const int base = (j / NS) * NS * R + k;
+        Butterfly<R, SIGN, T>::run(v[k]);
+        const int base = (j / NS) * NS * R + kk;
 #pragma unroll
-      for (int s = 0; s < R; ++s) buf[(base + s * NS) * NF + f] = v[p][s];
+        for (int s = 0; s < R; ++s) dst[lds_pad(base + s * NS) * NF + f] = v[k][s];
+      }
+    }
+    __syncthreads();
+  }
+
+  template <int NF, int PP>
+  static __device__ __forceinline__ void mids(C2<T>* a, C2<T>* b, const C2<T>* __restrict__ W, int t, int f,
+                                              bool inplace) {
+    if constexpr (PP < P - 1) {
+      mid<NF, PP>(a, b, W, t, f, inplace);
+      mids<NF, PP + 1>(b, a, W, t, f, inplace);
     }
   }
-  __syncthreads();
-}
 
-template <typename T, int L, int NF, int TPF, int SIGN, int P>
-__device__ __forceinline__ void stockham_from(C2<T>* buf, const C2<T>* __restrict__ W, int t, int f) {
-  constexpr RadixList rl = make_radices(L);
-  static_assert(rl.n > 0, "unsupported transform length");
-  if constexpr (P < rl.n) {
-    constexpr int R = rl.r[P];
-    constexpr int NS = radix_product(rl, P);
-    stockham_pass<T, L, NF, TPF, SIGN, R, NS>(buf, W, t, f);
-    stockham_from<T, L, NF, TPF, SIGN, P + 1>(buf, W, t, f);
+  // buffer the data ends in after the middle passes (for the last pass)
+  static constexpr bool ENDS_IN_B = ((P - 2) % 2) == 1;
+
+  // Full transform.  a, b: LDS buffers of lds_len<L>() * NF elements each
+  // (b may equal a: in-place mode, two barriers per exchange).  Ends with a
+  // barrier, so the buffers may be reused at once.
+  template <int NF>
+  static __device__ __forceinline__ void run(In& v0, Out& vn, C2<T>* a, C2<T>* b, const C2<T>* __restrict__ W, int t,
+                                             int f) {
+    const bool inplace = (a == b);
+    if constexpr (P == 1) {
+#pragma unroll
+      for (int k = 0; k < PER0; ++k) {
+        Butterfly<R0, SIGN, T>::run(v0[k]);
+#pragma unroll
+        for (int s = 0; s < R0; ++s) vn[k][s] = v0[k][s];
+      }
+      return;
+    } else {
+      // first pass: NS = 1, no twiddles; outputs j R0 + s
+      {
+        constexpr int NB = L / R0;
+#pragma unroll
+        for (int k = 0; k < PER0; ++k) {
+          const int j = t + k * TPF;
+          if (NB % TPF == 0 || j < NB) {
+            Butterfly<R0, SIGN, T>::run(v0[k]);
+#pragma unroll
+            for (int s = 0; s < R0; ++s) a[lds_pad(j * R0 + s) * NF + f] = v0[k][s];
+          }
+        }
+        __syncthreads();
+      }
+      mids<NF, 1>(a, b, W, t, f, inplace);
+      // last pass: NS = L / RN; outputs j + s L/RN
+      {
+        const C2<T>* src = ENDS_IN_B ? b : a;
+        constexpr int NS = L / RN;
+        constexpr int NB = L / RN;
+#pragma unroll
+        for (int k = 0; k < PERN; ++k) {
+          const int j = t + k * TPF;
+          if (NB % TPF == 0 || j < NB) {
+#pragma unroll
+            for (int q = 0; q < RN; ++q) vn[k][q] = src[lds_pad(j + q * NB) * NF + f];
+#pragma unroll
+            for (int q = 1; q < RN; ++q) {
+              C2<T> w = W[(q * j * (L / (NS * RN))) % L];
+              if (SIGN > 0) w.y = -w.y;
+              vn[k][q] = cmul(vn[k][q], w);
+            }
+            Butterfly<RN, SIGN, T>::run(vn[k]);
+          }
+        }
+        __syncthreads();
+      }
+    }
   }
-}
 
-// Transform NF sequences of length L held in LDS.  The workgroup must have
-// exactly NF * TPF threads, all of which call this (it contains barriers).
-template <typename T, int L, int NF, int TPF, int SIGN>
-__device__ __forceinline__ void fft_lds(C2<T>* buf, const C2<T>* __restrict__ W, int t, int f) {
-  stockham_from<T, L, NF, TPF, SIGN, 0>(buf, W, t, f);
-}
+  // element index held in register slot [k][q] before / after the transform
+  static __device__ __forceinline__ int in_index(int t, int k, int q) { return t + k * TPF + q * (L / R0); }
+  static __device__ __forceinline__ int out_index(int t, int k, int s) { return t + k * TPF + s * (L / RN); }
+  static __device__ __forceinline__ bool in_valid(int t, int k) { return (L / R0) % TPF == 0 || t + k * TPF < L / R0; }
+  static __device__ __forceinline__ bool out_valid(int t, int k) { return (L / RN) % TPF == 0 || t + k * TPF < L / RN; }
+};
 
 }  // namespace tc

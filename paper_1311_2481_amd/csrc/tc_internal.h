@@ -95,7 +95,7 @@ tc_status hip_check(tc_ctx* c, hipError_t e, const char* what);
 hipError_t launch_factor(tc_ctx* c, int* bad_dev);
 hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x);
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev_scratch,
-                     cd* u_next, cd* p);
+                     cd* u_next, cd* p, int want_p);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

@@ -96,22 +96,23 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
 }
 
 // ------------------------------------------------------------------ launch shapes
-// z kernels: NF columns per workgroup, TPF threads per column (NF * TPF threads).
+// z kernels: NF columns per workgroup, TPF threads per column; in-place LDS.
 template <typename T, int L> struct ZShape {
   static constexpr int TPF = L >= 512 ? (sizeof(T) == 8 ? 128 : 64) : (L >= 128 ? 32 : 8);
-  // at most 48 KB of LDS per workgroup, so that three workgroups share a CU
-  // and one's transform overlaps another's loads and stores
-  static constexpr int LDS_CAP = 49152;
+  // at most ~56 KB of LDS per workgroup so that two or more share a CU and
+  // one's transform overlaps another's loads and stores
+  static constexpr int LDS_CAP = 57344;
   static constexpr int NF0 = 256 / TPF;
-  static constexpr int NF1 = LDS_CAP / (L * (int)sizeof(C2<T>));
+  static constexpr int NF1 = LDS_CAP / (lds_len<L>() * (int)sizeof(C2<T>));
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
   static_assert(NF >= 1, "transform too long for LDS");
+  static constexpr size_t LDS = (size_t)lds_len<L>() * NF * sizeof(C2<T>);
 };
-// theta kernel: TPF threads per row, RPB rows per workgroup.
-template <int L> struct TShape {
+// theta kernel: TPF threads per row, RPB rows per workgroup; ping-pong LDS.
+template <typename T, int L> struct TShape {
   static constexpr int TPF = (L % 6 == 0) ? L / 6 : L / 8;
   static constexpr int RPB = TPF >= 256 ? 1 : 256 / TPF;
-  static constexpr int PTS = L / TPF;
+  static constexpr size_t LDS = 2 * (size_t)lds_len<L>() * RPB * sizeof(C2<T>);
 };
 
 // Workgroup id -> logical tile: consecutive ids go to different XCDs (8 of
@@ -125,11 +126,14 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 
 // ------------------------------------------------------------------ z inverse
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, const cd* __restrict__ u,
-                                                                             const cd* __restrict__ om,
-                                                                             C2<T>* __restrict__ inter,
-                                                                             const C2<T>* __restrict__ W) {
-  constexpr int NF = ZShape<T, L>::NF, TPF = ZShape<T, L>::TPF;
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0,
+                                                                               const cd* __restrict__ u,
+                                                                               const cd* __restrict__ om,
+                                                                               C2<T>* __restrict__ inter,
+                                                                               const C2<T>* __restrict__ W) {
+  using Z = ZShape<T, L>;
+  constexpr int NF = Z::NF, TPF = Z::TPF;
+  using FI = Fft<T, L, TPF, +1, false>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
@@ -142,31 +146,46 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
   const bool valid = n < d.mt;
   const cd* src = (fld < 3 ? u + fld * d.F : om + (fld - 3) * d.F) + (int64_t)(plane0 + pl) * d.S;
   const int h = d.half;
-  for (int e = t; e < L; e += TPF) {
-    int s = -1;
-    if (e < h) s = e;
-    else if (e > L - h) s = d.mz - (L - e);
-    C2<T> v = {T(0), T(0)};
-    if (s >= 0 && valid) {
-      const cd x = src[(int64_t)s * d.mt + n];
-      v = {T(x.x), T(x.y)};
+  typename FI::In v0;
+  typename FI::Out vo;
+#pragma unroll
+  for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::R0; ++q) {
+      const int e = FI::in_index(t, k, q);
+      int sl = -1;
+      if (e < h) sl = e;
+      else if (e > L - h) sl = d.mz - (L - e);
+      C2<T> v = {T(0), T(0)};
+      if (sl >= 0 && valid && FI::in_valid(t, k)) {
+        const cd x = src[(int64_t)sl * d.mt + n];
+        v = {T(x.x), T(x.y)};
+      }
+      v0[k][q] = v;
     }
-    buf[e * NF + f] = v;
-  }
-  __syncthreads();
-  fft_lds<T, L, NF, TPF, +1>(buf, W, t, f);
-  C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt;
-  if (valid)
-    for (int e = t; e < L; e += TPF) dst[(int64_t)e * d.mt + n] = buf[e * NF + f];
+  FI::template run<NF>(v0, vo, buf, buf, W, t, f);
+  if (!valid) return;
+  C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+    if (FI::out_valid(t, k))
+#pragma unroll
+      for (int s2 = 0; s2 < FI::RN; ++s2) dst[(int64_t)FI::out_index(t, k, s2) * d.mt] = vo[k][s2];
 }
 
 // ------------------------------------------------------------------ theta pass
 template <typename T, int L>
-__global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter,
-                                                                          const C2<T>* __restrict__ W) {
-  constexpr int TPF = TShape<L>::TPF, RPB = TShape<L>::RPB, PTS = TShape<L>::PTS;
+__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_theta(Dims d, int nplanes,
+                                                                                 C2<T>* __restrict__ inter,
+                                                                                 const C2<T>* __restrict__ W) {
+  using TS = TShape<T, L>;
+  constexpr int TPF = TS::TPF, RPB = TS::RPB;
+  using FI = Fft<T, L, TPF, +1, false>;
+  using FF = Fft<T, L, TPF, -1, true>;
+  static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
   extern __shared__ unsigned char lds_raw[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+  C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
+  C2<T>* bufb = bufa + lds_len<L>() * RPB;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -177,88 +196,98 @@ __global__ __launch_bounds__((TShape<L>::TPF * TShape<L>::RPB)) void k_theta(Dim
   C2<T>* base = inter + (int64_t)pl * 6 * fstride + (int64_t)z * d.mt;
   const int mt = d.mt;
 
-  // which = 0: h_u from (u+, u-); 1: h_omega from (omega+, omega-);
-  // 2: g = u_z + i omega_z.  Each: assemble the +-n spectrum, inverse
-  // transform, keep this thread's PTS points in registers.
-  auto inverse = [&](int which, C2<T>* out) {
+  // spectrum of h_u (which 0), h_omega (1) or g = u_z + i omega_z (2) at
+  // azimuthal index e (n = e or e - L)
+  auto spec = [&](int which, int e) -> C2<T> {
     const C2<T>* A = base + (int64_t)(which == 0 ? 0 : (which == 1 ? 3 : 2)) * fstride;
     const C2<T>* B = base + (int64_t)(which == 0 ? 1 : (which == 1 ? 4 : 5)) * fstride;
-    for (int e = t; e < L; e += TPF) {
-      const int nn = (e <= L / 2) ? e : e - L;
-      C2<T> v = {T(0), T(0)};
-      if (valid) {
-        if (which < 2) {
-          if (nn > 0 && nn < mt) v = A[nn];
-          else if (nn < 0 && -nn < mt) v = cconj(B[-nn]);
-          else if (nn == 0) {
-            const C2<T> p0 = A[0], m0 = B[0];
-            v = {T(0.5) * (p0.x + m0.x), T(0.5) * (p0.y - m0.y)};
-          }
-        } else {
-          if (nn > 0 && nn < mt) {
-            const C2<T> x = A[nn], y = B[nn];
-            v = {x.x - y.y, x.y + y.x};
-          } else if (nn < 0 && -nn < mt) {
-            const C2<T> x = cconj(A[-nn]), y = cconj(B[-nn]);
-            v = {x.x - y.y, x.y + y.x};
-          } else if (nn == 0) {
-            v = {A[0].x, B[0].x};
-          }
-        }
+    const int nn = (e <= L / 2) ? e : e - L;
+    C2<T> v = {T(0), T(0)};
+    if (!valid) return v;
+    if (which < 2) {
+      if (nn > 0 && nn < mt) v = A[nn];
+      else if (nn < 0 && -nn < mt) v = cconj(B[-nn]);
+      else if (nn == 0) {
+        const C2<T> p0 = A[0], m0 = B[0];
+        v = {T(0.5) * (p0.x + m0.x), T(0.5) * (p0.y - m0.y)};
       }
-      buf[e * RPB + f] = v;
+    } else {
+      if (nn > 0 && nn < mt) {
+        const C2<T> x = A[nn], y = B[nn];
+        v = {x.x - y.y, x.y + y.x};
+      } else if (nn < 0 && -nn < mt) {
+        const C2<T> x = cconj(A[-nn]), y = cconj(B[-nn]);
+        v = {x.x - y.y, x.y + y.x};
+      } else if (nn == 0) {
+        v = {A[0].x, B[0].x};
+      }
     }
-    __syncthreads();
-    fft_lds<T, L, RPB, TPF, +1>(buf, W, t, f);
-#pragma unroll
-    for (int k = 0; k < PTS; ++k) out[k] = buf[(t + k * TPF) * RPB + f];
-    __syncthreads();
+    return v;
   };
-  C2<T> hu[PTS], hw[PTS], g[PTS];
+  typename FI::In v0;
+  typename FI::Out hu, hw, g;
+  auto inverse = [&](int which, typename FI::Out& out) {
+#pragma unroll
+    for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+      for (int q = 0; q < FI::R0; ++q)
+        v0[k][q] = FI::in_valid(t, k) ? spec(which, FI::in_index(t, k, q)) : C2<T>{T(0), T(0)};
+    FI::template run<RPB>(v0, out, bufa, bufb, W, t, f);
+  };
   inverse(0, hu);
   inverse(1, hw);
   inverse(2, g);
-  // products at the PTS points e = t + k TPF held by this thread
-  C2<T> hn[PTS];
-  T nz[PTS];
+  // pointwise products (the slots hold the same points for all three)
+  typename FF::In hn, nz;
 #pragma unroll
-  for (int k = 0; k < PTS; ++k) {
-    const T uzv = g[k].x, wzv = g[k].y;
-    hn[k] = {uzv * hw[k].y - wzv * hu[k].y, wzv * hu[k].x - uzv * hw[k].x};
-    nz[k] = hw[k].x * hu[k].y - hw[k].y * hu[k].x;
-  }
-  // forward transform of N_r + i N_theta -> N+ (n >= 0) and conj(N-(-n))
+  for (int k = 0; k < FI::PERN; ++k)
 #pragma unroll
-  for (int k = 0; k < PTS; ++k) buf[(t + k * TPF) * RPB + f] = hn[k];
-  __syncthreads();
-  fft_lds<T, L, RPB, TPF, -1>(buf, W, t, f);
+    for (int q = 0; q < FI::RN; ++q) {
+      const C2<T> a = hu[k][q], w = hw[k][q];
+      const T uzv = g[k][q].x, wzv = g[k][q].y;
+      hn[k][q] = {uzv * w.y - wzv * a.y, wzv * a.x - uzv * w.x};
+      nz[k][q] = {w.x * a.y - w.y * a.x, T(0)};
+    }
+  typename FF::Out o;
+  FF::template run<RPB>(hn, o, bufa, bufb, W, t, f);
   if (valid) {
     C2<T>* Bp = base;
     C2<T>* Bm = base + fstride;
-    for (int nn = t; nn < mt; nn += TPF) {
-      Bp[nn] = buf[nn * RPB + f];
-      Bm[nn] = cconj(buf[((L - nn) % L) * RPB + f]);
-    }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PTS; ++k) buf[(t + k * TPF) * RPB + f] = C2<T>{nz[k], T(0)};
-  __syncthreads();
-  fft_lds<T, L, RPB, TPF, -1>(buf, W, t, f);
+    for (int k = 0; k < FF::PERN; ++k)
+      if (FF::out_valid(t, k))
+#pragma unroll
+        for (int s2 = 0; s2 < FF::RN; ++s2) {
+          const int e = FF::out_index(t, k, s2);
+          if (e < mt) Bp[e] = o[k][s2];
+          if (e == 0) Bm[0] = cconj(o[k][s2]);
+          else if (L - e < mt) Bm[L - e] = cconj(o[k][s2]);
+        }
+  }
+  FF::template run<RPB>(nz, o, bufa, bufb, W, t, f);
   if (valid) {
     C2<T>* Bz = base + 2 * fstride;
-    for (int nn = t; nn < mt; nn += TPF) Bz[nn] = buf[nn * RPB + f];
+#pragma unroll
+    for (int k = 0; k < FF::PERN; ++k)
+      if (FF::out_valid(t, k))
+#pragma unroll
+        for (int s2 = 0; s2 < FF::RN; ++s2) {
+          const int e = FF::out_index(t, k, s2);
+          if (e < mt) Bz[e] = o[k][s2];
+        }
   }
 }
 
 // ------------------------------------------------------------------ z forward
 template <typename T, int L>
 __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0,
-                                                                             const C2<T>* __restrict__ inter,
-                                                                             cd* __restrict__ N,
-                                                                             const C2<T>* __restrict__ W,
-                                                                             double scale) {
-  constexpr int NF = ZShape<T, L>::NF, TPF = ZShape<T, L>::TPF;
+                                                                               const C2<T>* __restrict__ inter,
+                                                                               cd* __restrict__ N,
+                                                                               const C2<T>* __restrict__ W,
+                                                                               double scale) {
+  using Z = ZShape<T, L>;
+  constexpr int NF = Z::NF, TPF = Z::TPF;
+  using FF = Fft<T, L, TPF, -1, false>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
@@ -269,22 +298,33 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int n = tile * NF + f;
   const bool valid = n < d.mt;
-  const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt;
-  for (int e = t; e < L; e += TPF) buf[e * NF + f] = valid ? src[(int64_t)e * d.mt + n] : C2<T>{T(0), T(0)};
-  __syncthreads();
-  fft_lds<T, L, NF, TPF, -1>(buf, W, t, f);
+  const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+  typename FF::In v0;
+  typename FF::Out vo;
+#pragma unroll
+  for (int k = 0; k < FF::PER0; ++k)
+#pragma unroll
+    for (int q = 0; q < FF::R0; ++q)
+      v0[k][q] = (valid && FF::in_valid(t, k)) ? src[(int64_t)FF::in_index(t, k, q) * d.mt] : C2<T>{T(0), T(0)};
+  FF::template run<NF>(v0, vo, buf, buf, W, t, f);
   if (!valid) return;
-  cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S;
+  cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S + n;
   const int h = d.half;
-  for (int s = t; s < d.mz; s += TPF) {
-    cd v = {0.0, 0.0};
-    if (s != h) {
-      const int e = s < h ? s : L - (d.mz - s);
-      const C2<T> x = buf[e * NF + f];
-      v = {double(x.x) * scale, double(x.y) * scale};
-    }
-    dst[(int64_t)s * d.mt + n] = v;
-  }
+#pragma unroll
+  for (int k = 0; k < FF::PERN; ++k)
+    if (FF::out_valid(t, k))
+#pragma unroll
+      for (int s2 = 0; s2 < FF::RN; ++s2) {
+        const int e = FF::out_index(t, k, s2);
+        int sl = -1;
+        if (e < h) sl = e;
+        else if (e > L - h) sl = d.mz - (L - e);
+        if (sl >= 0) {
+          const C2<T> x = vo[k][s2];
+          dst[(int64_t)sl * d.mt] = cd{double(x.x) * scale, double(x.y) * scale};
+        }
+      }
+  if (t == 0) dst[(int64_t)h * d.mt] = cd{0.0, 0.0};
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -305,7 +345,7 @@ size_t inter_bytes_per_plane(const tc_ctx* c) {
 template <typename T, int L>
 static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om, const C2<T>* W) {
   using Z = ZShape<T, L>;
-  const size_t lds = (size_t)L * Z::NF * sizeof(C2<T>);
+  const size_t lds = Z::LDS;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zinv<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -321,8 +361,8 @@ static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd*
 
 template <typename T, int L>
 static hipError_t run_theta(tc_ctx* c, int np, const C2<T>* W) {
-  using TS = TShape<L>;
-  const size_t lds = (size_t)L * TS::RPB * sizeof(C2<T>);
+  using TS = TShape<T, L>;
+  const size_t lds = TS::LDS;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_theta<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -339,7 +379,7 @@ static hipError_t run_theta(tc_ctx* c, int np, const C2<T>* W) {
 template <typename T, int L>
 static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, cd* N, const C2<T>* W) {
   using Z = ZShape<T, L>;
-  const size_t lds = (size_t)L * Z::NF * sizeof(C2<T>);
+  const size_t lds = Z::LDS;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zfwd<T, L>), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -259,284 +259,289 @@ __device__ __forceinline__ cd wall_vr(const double* R, double a, double b, const
 }
 
 // Sweeps (rows j = 0..M):
-//  1 ascending : RHS of the pressure Poisson problem, forward sweep of P  -> y_p   (in p)
+//  1 ascending : Ne = 2 N^i - N^{i-1} (kept in N_prev); RHS of the pressure
+//                Poisson problem; forward sweep of P                      -> y_p   (in p)
 //  2 descending: p* by back-substitution; RHS of the 3 Helmholtz problems;
 //                first (descending) sweep of H+, H-, H_z                 -> z     (in u_next), p* (in p)
 //  3 ascending : u* by the second sweep; RHS of phi; forward sweep of P  -> u* (in u_next), y_phi (in N_prev[0])
 //  4 descending: phi by back-substitution; correction and pressure update -> u^{i+1} (in u_next), p
-// Stencil terms lag the sweep by 4 rows (the D1 stencil spans +-4 rows).
-__global__ __launch_bounds__(64) void k_pc(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
-                                           const cd* __restrict__ u, const cd* up, const cd* __restrict__ N,
-                                           cd* Np, cd* un, cd* p) {
-  ModeLane L;
-  if (!make_lane(d, L)) return;
+// Stencil terms lag the sweep by 4 rows (the D1 stencil spans +-4 rows);
+// in the ascending sweeps D1 is applied in scatter form (each new row adds
+// its contribution to the 9 rows it touches), so no input window is kept.
+// want_p = 0 skips the pressure update (p then holds scratch).
+//
+// Lane layout: one mode per lane.  A wave holds 32 mode pairs: lanes 0-31
+// take slot +l, lanes 32-63 slot -l of the same (|l|, n), so both halves
+// load the same factor words in the same instruction (one fetch) and every
+// state access is two contiguous 32-element runs.  The -l lanes of |l| = 0
+// are idle (that slot is the +l one).
+struct Lane1 {
+  int dm;          // distinct mode (factor column)
+  int64_t o;       // plane offset of the slot
+  double a, b;
+  bool zero_mode;
+};
+
+__device__ __forceinline__ bool make_lane1(const Dims& d, Lane1& L) {
+  const int half = threadIdx.x >> 5;
+  L.dm = blockIdx.x * 32 + (threadIdx.x & 31);
+  if (L.dm >= d.ndm) return false;
+  const int labs = L.dm / d.mt, n = L.dm - labs * d.mt;
+  if (half == 1 && labs == 0) return false;
+  const int s = half ? d.mz - labs : labs;
+  L.o = (int64_t)s * d.mt + n;
+  L.a = n * d.kt;
+  L.b = (half ? -labs : labs) * d.kz;
+  L.zero_mode = (labs == 0 && n == 0);
+  return true;
+}
+
+#define TC_PC_ARGS                                                                                              \
+  const double *__restrict__ rc, const double *__restrict__ fac, Dims d, const cd *__restrict__ u, const cd *up, \
+      const cd *__restrict__ N, cd *Np, cd *un, cd *p, int want_p
+
+__global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
+  Lane1 L;
+  if (!make_lane1(d, L)) return;
   const int M = d.n_r - 1;
   const int64_t F = d.F, S = d.S;
   const double a = L.a;
-  // |l| = 0 has a single slot: its second "mode" would alias the first
-  // (read-modify-write of the same words), so it is skipped throughout.
-  const bool two = L.labs != 0;
+  // Wall rows of the consistent Neumann condition: 2 V_r(u^i) - V_r(u^{i-1})
+  // = V_r(2 u^i - u^{i-1}), V_r = (L+ u+ + L- u-)/2, accumulated while the
+  // sweep passes the 5 rows next to each wall.
+  cd bc0 = cz(), bcM = cz();
+  cd acc[NB9], yw[4], ner0 = cz(), nerM = cz();
+  for (int k = 0; k < NB9; ++k) acc[k] = cz();
+  for (int q = 0; q < 4; ++q) yw[q] = cz();
+  for (int j = 0; j <= M + HW; ++j) {
+    if (j <= M) {
+      const double ir = rc[(int64_t)j * RC_N + RC_IR];
+      const int64_t o = j * S + L.o;
+      if (j <= HW || j >= M - HW) {
+        const cd vp = csub(cmuls(u[o], 2.0), up[o]);
+        const cd vm = csub(cmuls(u[F + o], 2.0), up[F + o]);
+        const cd sum = cadd(vp, vm), dif = csub(vp, vm);
+#pragma unroll
+        for (int wsel = 0; wsel < 2; ++wsel) {
+          const int jw = wsel ? M : 0;
+          const int k = j - jw + HW;
+          if (k < 0 || k >= NB9) continue;
+          const double* R = rc + (int64_t)jw * RC_N;
+          cd t = cmuls(sum, 0.5 * (R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR]));
+          if (k == HW) {
+            t = cfma(t, 0.5 * (-(a * a + 1.0) * R[RC_IR2] - L.b * L.b), sum);
+            t = cfma(t, -a * R[RC_IR2], dif);
+          }
+          if (wsel) bcM = cadd(bcM, t); else bc0 = cadd(bc0, t);
+        }
+      }
+      const cd ep = csub(cmuls(N[o], 2.0), Np[o]);
+      const cd em = csub(cmuls(N[F + o], 2.0), Np[F + o]);
+      const cd ez = csub(cmuls(N[2 * F + o], 2.0), Np[2 * F + o]);
+      Np[o] = ep;
+      Np[F + o] = em;
+      Np[2 * F + o] = ez;
+      const cd er = cmuls(cadd(ep, em), 0.5);
+      if (j == 0) ner0 = er;
+      if (j == M) nerM = er;
+      // D1 scatter: row j feeds rows i = j-4..j+4 (slot k = i - j + 4)
+#pragma unroll
+      for (int k = 0; k < NB9; ++k) {
+        const int i = j - HW + k;
+        if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], er);
+      }
+      cd l = cmuls(er, ir);
+      l = cfma(l, 0.5 * a * ir, csub(ep, em));
+      l = cadd(l, cimul(ez, L.b));
+      acc[HW] = cadd(acc[HW], l);
+    }
+    const int i = j - HW;
+    if (i >= 0) {
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+      cd rhs;
+      if (i == 0) rhs = cmuls(csub(bc0, ner0), d.s0);
+      else if (i == M) rhs = L.zero_mode ? cz() : cmuls(csub(bcM, nerM), d.sM);
+      else rhs = cd{-acc[0].x, -acc[0].y};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yw[q]);
+      for (int q = 3; q >= 1; --q) yw[q] = yw[q - 1];
+      yw[0] = rhs;
+      p[i * S + L.o] = rhs;
+    }
+    for (int k = 0; k < NB9 - 1; ++k) acc[k] = acc[k + 1];
+    acc[NB9 - 1] = cz();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
+  Lane1 L;
+  if (!make_lane1(d, L)) return;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const double a = L.a;
   const double c_dt = 1.0 / (2.0 * d.dt);
-
-  // ---- wall rows of the consistent Neumann condition: 2 V_r(u^i) - V_r(u^{i-1})
-  cd bc[2][2];  // [wall][mode]
-  for (int wsel = 0; wsel < 2; ++wsel) {
-    const int j = wsel ? M : 0;
-    const int kbeg = wsel ? 0 : HW;
-    const double* R = rc + (int64_t)j * RC_N;
-    for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-      cd vp[5], vm[5], wp[5], wm[5];
-      for (int t = 0; t < 5; ++t) {
-        const int node = j + kbeg + t - HW;
-        const int64_t o = node * S + L.o[m];
-        vp[t] = u[o]; vm[t] = u[F + o];
-        wp[t] = up[o]; wm[t] = up[F + o];
-      }
-      const cd v1 = wall_vr(R, a, L.b[m], vp, vm, kbeg);
-      const cd v0 = wall_vr(R, a, L.b[m], wp, wm, kbeg);
-      bc[wsel][m] = cd{2.0 * v1.x - v0.x, 2.0 * v1.y - v0.y};
+  cd pw[NB9], zw[3][4];
+  for (int k = 0; k < NB9; ++k) pw[k] = cz();
+  for (int o = 0; o < 3; ++o)
+    for (int q = 0; q < 4; ++q) zw[o][q] = cz();
+  for (int jj = M; jj >= -HW; --jj) {
+    for (int k = NB9 - 1; k >= 1; --k) pw[k] = pw[k - 1];
+    if (jj >= 0) {
+      const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
+      cd y = p[jj * S + L.o];
+#pragma unroll
+      for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], pw[c]);
+      y = cmuls(y, Fp[(int64_t)4 * d.ndm]);
+      pw[0] = y;
+      if (want_p) p[jj * S + L.o] = y;
+    } else {
+      pw[0] = cz();
     }
-  }
-
-  // ---- sweep 1 (ascending)
-  {
-    cd win[NB9][2], loc[5][2], yw[4][2];
-    for (int k = 0; k < NB9; ++k) win[k][0] = win[k][1] = cz();
-    for (int k = 0; k < 5; ++k) loc[k][0] = loc[k][1] = cz();
-    for (int q = 0; q < 4; ++q) yw[q][0] = yw[q][1] = cz();
-    for (int j = 0; j <= M + HW; ++j) {
-      for (int k = 0; k < NB9 - 1; ++k) { win[k][0] = win[k + 1][0]; win[k][1] = win[k + 1][1]; }
-      for (int k = 0; k < 4; ++k) { loc[k][0] = loc[k + 1][0]; loc[k][1] = loc[k + 1][1]; }
-      if (j <= M) {
-        const double ir = rc[(int64_t)j * RC_N + RC_IR];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-          const int64_t o = j * S + L.o[m];
-          const cd ep = csub(cmuls(N[o], 2.0), Np[o]);
-          const cd em = csub(cmuls(N[F + o], 2.0), Np[F + o]);
-          const cd ez = csub(cmuls(N[2 * F + o], 2.0), Np[2 * F + o]);
-          const cd er = cmuls(cadd(ep, em), 0.5);
-          win[NB9 - 1][m] = er;
-          cd l = cmuls(er, ir);
-          l = cfma(l, 0.5 * a * ir, csub(ep, em));
-          l = cadd(l, cimul(ez, L.b[m]));
-          loc[4][m] = l;
-        }
-      } else {
-        win[NB9 - 1][0] = win[NB9 - 1][1] = cz();
-      }
-      const int i = j - HW;
-      if (i < 0) continue;
-      const double* R = rc + (int64_t)i * RC_N;
-      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-        cd rhs;
-        if (i == 0) {
-          rhs = cmuls(csub(bc[0][m], win[HW][m]), d.s0);
-        } else if (i == M) {
-          rhs = L.zero_mode ? cz() : cmuls(csub(bc[1][m], win[HW][m]), d.sM);
-        } else {
-          cd dd = loc[0][m];
-#pragma unroll
-          for (int k = 0; k < NB9; ++k) dd = cfma(dd, R[RC_W1 + k], win[k][m]);
-          rhs = cd{-dd.x, -dd.y};
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yw[q][m]);
-        for (int q = 3; q >= 1; --q) yw[q][m] = yw[q - 1][m];
-        yw[0][m] = rhs;
-        p[i * S + L.o[m]] = rhs;
-      }
-    }
-  }
-
-  // ---- sweep 2 (descending)
-  {
-    cd pw[NB9][2], zw[3][4][2];
-    for (int k = 0; k < NB9; ++k) pw[k][0] = pw[k][1] = cz();
-    for (int o = 0; o < 3; ++o)
-      for (int q = 0; q < 4; ++q) zw[o][q][0] = zw[o][q][1] = cz();
-    for (int jj = M; jj >= -HW; --jj) {
-      for (int k = NB9 - 1; k >= 1; --k) { pw[k][0] = pw[k - 1][0]; pw[k][1] = pw[k - 1][1]; }
-      if (jj >= 0) {
-        const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
-        const double inv = Fp[(int64_t)4 * d.ndm];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-          cd y = p[jj * S + L.o[m]];
-#pragma unroll
-          for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], pw[c][m]);
-          y = cmuls(y, inv);
-          pw[0][m] = y;
-          p[jj * S + L.o[m]] = y;
-        }
-      } else {
-        pw[0][0] = pw[0][1] = cz();
-      }
-      const int i = jj + HW;
-      if (i > M) continue;
-      const double* R = rc + (int64_t)i * RC_N;
-      const double ir = R[RC_IR];
-      const bool wall = (i == 0 || i == M);
+    const int i = jj + HW;
+    if (i > M) continue;
+    const double* R = rc + (int64_t)i * RC_N;
+    const double ir = R[RC_IR];
+    cd rhs[3];
+    if (i == 0 || i == M) {
       const double Re = (i == 0) ? d.Re_i : d.Re_o;
+      rhs[0] = L.zero_mode ? cd{0.0, Re} : cz();
+      rhs[1] = L.zero_mode ? cd{0.0, -Re} : cz();
+      rhs[2] = cz();
+    } else {
+      cd d1 = cz();
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-        cd rhs[3];
-        if (wall) {
-          rhs[0] = L.zero_mode ? cd{0.0, Re} : cz();
-          rhs[1] = L.zero_mode ? cd{0.0, -Re} : cz();
-          rhs[2] = cz();
-        } else {
-          cd d1 = cz();
+      for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], pw[k]);
+      const cd pi = pw[HW];
+      const int64_t o = i * S + L.o;
 #pragma unroll
-          for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], pw[k][m]);
-          const cd pi = pw[HW][m];
-          const int64_t o = i * S + L.o[m];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const cd ne = csub(cmuls(N[c * F + o], 2.0), Np[c * F + o]);
-            const cd ut = csub(cmuls(u[c * F + o], 4.0), up[c * F + o]);
-            cd r = cd{ne.x - ut.x * c_dt, ne.y - ut.y * c_dt};
-            if (c == 0) r = cadd(r, cnfma(d1, a * ir, pi));
-            if (c == 1) r = cadd(r, cfma(d1, a * ir, pi));
-            if (c == 2) r = cadd(r, cimul(pi, L.b[m]));
-            rhs[c] = r;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
-          cd z = rhs[c];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) z = cnfma(z, Fh[(int64_t)q * d.ndm], zw[c][q][m]);
-          for (int q = 3; q >= 1; --q) zw[c][q][m] = zw[c][q - 1][m];
-          zw[c][0][m] = z;
-          un[c * F + i * S + L.o[m]] = z;
-        }
+      for (int c = 0; c < 3; ++c) {
+        const cd ne = Np[c * F + o];
+        const cd ut = csub(cmuls(u[c * F + o], 4.0), up[c * F + o]);
+        cd r = cd{ne.x - ut.x * c_dt, ne.y - ut.y * c_dt};
+        if (c == 0) r = cadd(r, cnfma(d1, a * ir, pi));
+        if (c == 1) r = cadd(r, cfma(d1, a * ir, pi));
+        if (c == 2) r = cadd(r, cimul(pi, L.b));
+        rhs[c] = r;
       }
     }
-  }
-
-  // ---- sweep 3 (ascending)
-  {
-    cd xw[3][4][2], rw[NB9][2], lf[5][2], yp[4][2];
-    for (int c = 0; c < 3; ++c)
-      for (int q = 0; q < 4; ++q) xw[c][q][0] = xw[c][q][1] = cz();
-    for (int k = 0; k < NB9; ++k) rw[k][0] = rw[k][1] = cz();
-    for (int k = 0; k < 5; ++k) lf[k][0] = lf[k][1] = cz();
-    for (int q = 0; q < 4; ++q) yp[q][0] = yp[q][1] = cz();
-    for (int j = 0; j <= M + HW; ++j) {
-      for (int k = 0; k < NB9 - 1; ++k) { rw[k][0] = rw[k + 1][0]; rw[k][1] = rw[k + 1][1]; }
-      for (int k = 0; k < 4; ++k) { lf[k][0] = lf[k + 1][0]; lf[k][1] = lf[k + 1][1]; }
-      if (j <= M) {
-        const double ir = rc[(int64_t)j * RC_N + RC_IR];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-          cd xs[3];
+    for (int c = 0; c < 3; ++c) {
+      const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
+      cd z = rhs[c];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double* Fh = facp(fac, d, OP_HP + c, j) + L.dm;
-            const int64_t o = c * F + j * S + L.o[m];
-            cd y = un[o];
-#pragma unroll
-            for (int q = 1; q <= 4; ++q) y = cnfma(y, Fh[(int64_t)(4 + q) * d.ndm], xw[c][q - 1][m]);
-            y = cmuls(y, Fh[(int64_t)4 * d.ndm]);
-            for (int q = 3; q >= 1; --q) xw[c][q][m] = xw[c][q - 1][m];
-            xw[c][0][m] = y;
-            un[o] = y;
-            xs[c] = y;
-          }
-          const cd ur = cmuls(cadd(xs[0], xs[1]), 0.5);
-          rw[NB9 - 1][m] = ur;
-          cd l = cmuls(ur, ir);
-          l = cfma(l, 0.5 * a * ir, csub(xs[0], xs[1]));
-          l = cadd(l, cimul(xs[2], L.b[m]));
-          lf[4][m] = l;
-        }
-      } else {
-        rw[NB9 - 1][0] = rw[NB9 - 1][1] = cz();
-      }
-      const int i = j - HW;
-      if (i < 0) continue;
-      const double* R = rc + (int64_t)i * RC_N;
-      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-        cd rhs = cz();
-        if (i != 0 && i != M) {
-          rhs = lf[0][m];
-#pragma unroll
-          for (int k = 0; k < NB9; ++k) rhs = cfma(rhs, R[RC_W1 + k], rw[k][m]);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yp[q][m]);
-        for (int q = 3; q >= 1; --q) yp[q][m] = yp[q - 1][m];
-        yp[0][m] = rhs;
-        Np[i * S + L.o[m]] = rhs;
-      }
-    }
-  }
-
-  // ---- sweep 4 (descending)
-  {
-    cd fw[NB9][2];
-    for (int k = 0; k < NB9; ++k) fw[k][0] = fw[k][1] = cz();
-    const double c_p = 1.5 / d.dt;
-    for (int jj = M; jj >= -HW; --jj) {
-      for (int k = NB9 - 1; k >= 1; --k) { fw[k][0] = fw[k - 1][0]; fw[k][1] = fw[k - 1][1]; }
-      if (jj >= 0) {
-        const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
-        const double inv = Fp[(int64_t)4 * d.ndm];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-          cd y = Np[jj * S + L.o[m]];
-#pragma unroll
-          for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], fw[c][m]);
-          fw[0][m] = cmuls(y, inv);
-        }
-      } else {
-        fw[0][0] = fw[0][1] = cz();
-      }
-      const int i = jj + HW;
-      if (i > M) continue;
-      const double* R = rc + (int64_t)i * RC_N;
-      const double ir = R[RC_IR];
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) continue;
-        cd d1 = cz();
-#pragma unroll
-        for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k][m]);
-        const cd ph = fw[HW][m];
-        const int64_t o = i * S + L.o[m];
-        const cd gpl = cnfma(d1, a * ir, ph);
-        const cd gmi = cfma(d1, a * ir, ph);
-        un[o] = csub(un[o], gpl);
-        un[F + o] = csub(un[F + o], gmi);
-        un[2 * F + o] = csub(un[2 * F + o], cimul(ph, L.b[m]));
-        p[o] = cfma(p[o], c_p, ph);
-      }
-      if (L.labs == 0) {
-        const int64_t o = i * S + (int64_t)d.nyq * d.mt + L.n;
-        un[o] = cz(); un[F + o] = cz(); un[2 * F + o] = cz(); p[o] = cz();
-      }
+      for (int q = 0; q < 4; ++q) z = cnfma(z, Fh[(int64_t)q * d.ndm], zw[c][q]);
+      for (int q = 3; q >= 1; --q) zw[c][q] = zw[c][q - 1];
+      zw[c][0] = z;
+      un[c * F + i * S + L.o] = z;
     }
   }
 }
 
-hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p) {
-  const int blocks = (c->d.ndm + 63) / 64;
-  hipLaunchKernelGGL(k_pc, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, u, u_prev, N, N_prev,
-                     u_next, p);
+__global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
+  Lane1 L;
+  if (!make_lane1(d, L)) return;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const double a = L.a;
+  cd xw[3][4], acc[NB9], yp[4];
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 4; ++q) xw[c][q] = cz();
+  for (int k = 0; k < NB9; ++k) acc[k] = cz();
+  for (int q = 0; q < 4; ++q) yp[q] = cz();
+  for (int j = 0; j <= M + HW; ++j) {
+    if (j <= M) {
+      const double ir = rc[(int64_t)j * RC_N + RC_IR];
+      cd xs[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double* Fh = facp(fac, d, OP_HP + c, j) + L.dm;
+        const int64_t o = c * F + j * S + L.o;
+        cd y = un[o];
+#pragma unroll
+        for (int q = 1; q <= 4; ++q) y = cnfma(y, Fh[(int64_t)(4 + q) * d.ndm], xw[c][q - 1]);
+        y = cmuls(y, Fh[(int64_t)4 * d.ndm]);
+        for (int q = 3; q >= 1; --q) xw[c][q] = xw[c][q - 1];
+        xw[c][0] = y;
+        un[o] = y;
+        xs[c] = y;
+      }
+      const cd ur = cmuls(cadd(xs[0], xs[1]), 0.5);
+#pragma unroll
+      for (int k = 0; k < NB9; ++k) {
+        const int i = j - HW + k;
+        if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], ur);
+      }
+      cd l = cmuls(ur, ir);
+      l = cfma(l, 0.5 * a * ir, csub(xs[0], xs[1]));
+      l = cadd(l, cimul(xs[2], L.b));
+      acc[HW] = cadd(acc[HW], l);
+    }
+    const int i = j - HW;
+    if (i >= 0) {
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+      cd rhs = (i != 0 && i != M) ? acc[0] : cz();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yp[q]);
+      for (int q = 3; q >= 1; --q) yp[q] = yp[q - 1];
+      yp[0] = rhs;
+      Np[i * S + L.o] = rhs;
+    }
+    for (int k = 0; k < NB9 - 1; ++k) acc[k] = acc[k + 1];
+    acc[NB9 - 1] = cz();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
+  Lane1 L;
+  if (!make_lane1(d, L)) return;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const double a = L.a;
+  const double c_p = 1.5 / d.dt;
+  const bool nyq_lane = (L.dm < d.mt) && (threadIdx.x < 32);  // |l| = 0, +l half: clears the empty slot
+  cd fw[NB9];
+  for (int k = 0; k < NB9; ++k) fw[k] = cz();
+  for (int jj = M; jj >= -HW; --jj) {
+    for (int k = NB9 - 1; k >= 1; --k) fw[k] = fw[k - 1];
+    if (jj >= 0) {
+      const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
+      cd y = Np[jj * S + L.o];
+#pragma unroll
+      for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], fw[c]);
+      fw[0] = cmuls(y, Fp[(int64_t)4 * d.ndm]);
+    } else {
+      fw[0] = cz();
+    }
+    const int i = jj + HW;
+    if (i > M) continue;
+    const double* R = rc + (int64_t)i * RC_N;
+    const double ir = R[RC_IR];
+    cd d1 = cz();
+#pragma unroll
+    for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k]);
+    const cd ph = fw[HW];
+    const int64_t o = i * S + L.o;
+    un[o] = csub(un[o], cnfma(d1, a * ir, ph));
+    un[F + o] = csub(un[F + o], cfma(d1, a * ir, ph));
+    un[2 * F + o] = csub(un[2 * F + o], cimul(ph, L.b));
+    if (want_p) p[o] = cfma(p[o], c_p, ph);
+    if (nyq_lane) {
+      const int64_t on = i * S + (int64_t)d.nyq * d.mt + (L.dm % d.mt);
+      un[on] = cz(); un[F + on] = cz(); un[2 * F + on] = cz();
+      if (want_p) p[on] = cz();
+    }
+  }
+}
+
+hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
+                     int want_p) {
+  const int blocks = (c->d.ndm + 31) / 32;
+  for (auto* k : {k_pc1, k_pc2, k_pc3, k_pc4}) {
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, u, u_prev, N, N_prev,
+                       u_next, p, want_p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
