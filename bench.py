@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--workload", default="production")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -157,6 +159,13 @@ def main():
     from paper_1311_2481_amd import Solver
 
     cfg = tc_inputs.Config(tc_inputs.CONFIGS[args.workload])
+    if args.calibrate_copy:
+        n = args.calibrate_copy * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] workload {args.workload}: building the initial state on the GPU", file=sys.stderr, flush=True)
     # nodes from the library itself (no oracle on the product path)
     probe = Solver(cfg.n_r, 16, 32, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,

@@ -61,14 +61,28 @@ def plus_minus(vr, vt, vz):
     return np.stack([vr + 1j * vt, vr - 1j * vt, vz])
 
 
+def _curl(prob, r, ur, ut, uz, d_ut, d_uz):
+    """omega from the cylindrical components and their radial derivatives."""
+    a = prob.a[None, :]
+    b = prob.b[:, None]
+    wr = 1j * a * uz / r - 1j * b * ut
+    wt = 1j * b * ur - d_uz
+    wz = d_ut + ut / r - 1j * a * ur / r
+    return wr, wt, wz
+
+
 def vorticity(prob, u):
     """omega = curl u in cylindrical components, spectral in (theta, z), FD in r."""
     ur, ut, uz = cylindrical(u)
-    a, b, r = prob.bcast()
-    wr = 1j * a * uz / r - 1j * b * ut
-    wt = 1j * b * ur - prob.ddr(uz)
-    wz = prob.ddr(ut) + ut / r - 1j * a * ur / r
-    return wr, wt, wz
+    r = prob.r[:, None, None]
+    return _curl(prob, r, ur, ut, uz, prob.ddr(ut), prob.ddr(uz))
+
+
+def _omega_cross_u(prob, U, W):
+    Nr = W[1] * U[2] - W[2] * U[1]
+    Nt = W[2] * U[0] - W[0] * U[2]
+    Nz = W[0] * U[1] - W[1] * U[0]
+    return plus_minus(*to_spectral(prob, np.stack([Nr, Nt, Nz])))
 
 
 def nonlinear_rot(prob, u):
@@ -77,11 +91,25 @@ def nonlinear_rot(prob, u):
     wr, wt, wz = vorticity(prob, u)
     U = to_physical(prob, np.stack([ur, ut, uz]))
     W = to_physical(prob, np.stack([wr, wt, wz]))
-    Nr = W[1] * U[2] - W[2] * U[1]
-    Nt = W[2] * U[0] - W[0] * U[2]
-    Nz = W[0] * U[1] - W[1] * U[0]
-    S = to_spectral(prob, np.stack([Nr, Nt, Nz]))
-    return plus_minus(*S)
+    return _omega_cross_u(prob, U, W)
+
+
+def nonlinear_rot_at(prob, window, j):
+    """N = omega x u at radial node j only.
+
+    ``window`` holds the velocity at nodes max(0, j-4) .. min(M, j+4) (the
+    support of FD row j), shape (3, rows, m_z, m_theta).
+    """
+    lo = max(0, j - 4)
+    ur, ut, uz = cylindrical(window)
+    w = prob.D1[j, lo:lo + window.shape[1]]
+    d_ut = np.tensordot(w, ut, axes=(0, 0))
+    d_uz = np.tensordot(w, uz, axes=(0, 0))
+    k = j - lo
+    wr, wt, wz = _curl(prob, prob.r[j], ur[k], ut[k], uz[k], d_ut, d_uz)
+    U = to_physical(prob, np.stack([ur[k], ut[k], uz[k]]))
+    W = to_physical(prob, np.stack([wr, wt, wz]))
+    return _omega_cross_u(prob, U, W)
 
 
 def nonlinear_conv(prob, u):

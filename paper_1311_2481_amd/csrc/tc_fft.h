@@ -29,7 +29,10 @@
 
 namespace tc {
 
-template <typename T> struct C2 { T x, y; };
+// Aligned to its full size so that LDS and global accesses are single
+// 128-bit (double) or 64-bit (float) operations: split 64-bit accesses of
+// interleaved complex data would hit the LDS banks two-way.
+template <typename T> struct alignas(2 * sizeof(T)) C2 { T x, y; };
 
 template <typename T> __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }

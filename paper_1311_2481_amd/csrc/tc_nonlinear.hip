@@ -107,26 +107,44 @@ template <typename T, int L> struct ZShape {
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
   static_assert(NF >= 1, "transform too long for LDS");
   static constexpr size_t LDS = (size_t)lds_len<L>() * NF * sizeof(C2<T>);
+  // persistent workgroups prefetching the next tile: pays off when the
+  // prefetch registers do not lower the occupancy (float data)
+  static constexpr bool PREFETCH = sizeof(T) == 4;
 };
-// theta kernel: TPF threads per row, RPB rows per workgroup; ping-pong LDS.
+// theta kernel: TPF threads per row, RPB rows per workgroup; ping-pong
+// LDS (one barrier per exchange) or in place (two barriers, half the LDS).
+#ifndef TC_THETA_PINGPONG
+#define TC_THETA_PINGPONG 0
+#endif
 template <typename T, int L> struct TShape {
   static constexpr int TPF = (L % 6 == 0) ? L / 6 : L / 8;
   static constexpr int RPB = TPF >= 256 ? 1 : 256 / TPF;
-  static constexpr size_t LDS = 2 * (size_t)lds_len<L>() * RPB * sizeof(C2<T>);
+  static constexpr int NBUF = TC_THETA_PINGPONG ? 2 : 1;
+  static constexpr size_t LDS = NBUF * (size_t)lds_len<L>() * RPB * sizeof(C2<T>);
 };
 
-// Workgroup id -> logical tile: consecutive ids go to different XCDs (8 of
-// them, round robin), so remap to let each XCD walk a contiguous range of
-// tiles (neighbouring column tiles share cache lines).
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  const int per = nblocks / 8;
-  if (per == 0 || bid >= per * 8) return bid;
-  return (bid % 8) * per + bid / 8;
-}
+// Persistent z kernels: gridDim.x workgroups loop over all column tiles,
+// loading the next tile into registers while the current one is being
+// transformed (the LDS then never waits on memory).  Workgroups on one XCD
+// (8 of them, assigned round robin) take tiles of one contiguous range, so
+// neighbouring column tiles, which share cache lines, go through the same L2.
+struct TileWalk {
+  int xcd, per_xcd, first, last;
+  __device__ TileWalk(int ntiles) {
+    const int g = gridDim.x;
+    xcd = blockIdx.x % 8;
+    const int nx = (g + 7 - xcd) / 8;           // workgroups on this XCD
+    const int slot = blockIdx.x / 8;
+    const int lo = (int)((int64_t)ntiles * xcd / 8), hi = (int)((int64_t)ntiles * (xcd + 1) / 8);
+    per_xcd = nx;
+    first = lo + slot;
+    last = hi;
+  }
+};
 
 // ------------------------------------------------------------------ z inverse
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, int nplanes,
                                                                                const cd* __restrict__ u,
                                                                                const cd* __restrict__ om,
                                                                                C2<T>* __restrict__ inter,
@@ -137,40 +155,66 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = bid % tiles;
-  const int rest = bid / tiles;
-  const int fld = rest % 6, pl = rest / 6;
+  const int ntiles = tiles * 6 * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
-  const int n = tile * NF + f;
-  const bool valid = n < d.mt;
-  const cd* src = (fld < 3 ? u + fld * d.F : om + (fld - 3) * d.F) + (int64_t)(plane0 + pl) * d.S;
   const int h = d.half;
-  typename FI::In v0;
-  typename FI::Out vo;
+  TileWalk tw(ntiles);
+  auto load = [&](int id, cd (&raw)[FI::PER0][FI::R0]) {
+    const int tile = id % tiles, rest = id / tiles;
+    const int fld = rest % 6, pl = rest / 6;
+    const int n = tile * NF + f;
+    const cd* src = (fld < 3 ? u + fld * d.F : om + (fld - 3) * d.F) + (int64_t)(plane0 + pl) * d.S + n;
 #pragma unroll
-  for (int k = 0; k < FI::PER0; ++k)
+    for (int k = 0; k < FI::PER0; ++k)
 #pragma unroll
-    for (int q = 0; q < FI::R0; ++q) {
-      const int e = FI::in_index(t, k, q);
-      int sl = -1;
-      if (e < h) sl = e;
-      else if (e > L - h) sl = d.mz - (L - e);
-      C2<T> v = {T(0), T(0)};
-      if (sl >= 0 && valid && FI::in_valid(t, k)) {
-        const cd x = src[(int64_t)sl * d.mt + n];
-        v = {T(x.x), T(x.y)};
+      for (int q = 0; q < FI::R0; ++q) {
+        const int e = FI::in_index(t, k, q);
+        int sl = -1;
+        if (e < h) sl = e;
+        else if (e > L - h) sl = d.mz - (L - e);
+        raw[k][q] = (sl >= 0 && n < d.mt && FI::in_valid(t, k)) ? src[(int64_t)sl * d.mt] : cd{0.0, 0.0};
       }
-      v0[k][q] = v;
+  };
+  auto transform_store = [&](int id, cd (&raw)[FI::PER0][FI::R0]) {
+    typename FI::In v0;
+    typename FI::Out vo;
+#pragma unroll
+    for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+      for (int q = 0; q < FI::R0; ++q) v0[k][q] = C2<T>{T(raw[k][q].x), T(raw[k][q].y)};
+    FI::template run<NF>(v0, vo, buf, buf, W, t, f);
+    const int tile = id % tiles, rest = id / tiles;
+    const int fld = rest % 6, pl = rest / 6;
+    const int n = tile * NF + f;
+    if (n < d.mt) {
+      C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+#pragma unroll
+      for (int k = 0; k < FI::PERN; ++k)
+        if (FI::out_valid(t, k))
+#pragma unroll
+          for (int s2 = 0; s2 < FI::RN; ++s2) dst[(int64_t)FI::out_index(t, k, s2) * d.mt] = vo[k][s2];
     }
-  FI::template run<NF>(v0, vo, buf, buf, W, t, f);
-  if (!valid) return;
-  C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+  };
+  if constexpr (Z::PREFETCH) {
+    cd cur[FI::PER0][FI::R0], nxt[FI::PER0][FI::R0];
+    if (tw.first < tw.last) load(tw.first, cur);
+    for (int id = tw.first; id < tw.last; id += tw.per_xcd) {
+      const int idn = id + tw.per_xcd;
+      if (idn < tw.last) load(idn, nxt);
+      transform_store(id, cur);
 #pragma unroll
-  for (int k = 0; k < FI::PERN; ++k)
-    if (FI::out_valid(t, k))
+      for (int k = 0; k < FI::PER0; ++k)
 #pragma unroll
-      for (int s2 = 0; s2 < FI::RN; ++s2) dst[(int64_t)FI::out_index(t, k, s2) * d.mt] = vo[k][s2];
+        for (int q = 0; q < FI::R0; ++q) cur[k][q] = nxt[k][q];
+    }
+  } else {
+    // one tile per workgroup
+    cd cur[FI::PER0][FI::R0];
+    if (tw.first < tw.last) {
+      load(tw.first, cur);
+      transform_store(tw.first, cur);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ theta pass
@@ -185,7 +229,7 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
   static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
   extern __shared__ unsigned char lds_raw[];
   C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
-  C2<T>* bufb = bufa + lds_len<L>() * RPB;
+  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L>() * RPB : bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -280,7 +324,7 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
 
 // ------------------------------------------------------------------ z forward
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0, int nplanes,
                                                                                const C2<T>* __restrict__ inter,
                                                                                cd* __restrict__ N,
                                                                                const C2<T>* __restrict__ W,
@@ -291,40 +335,65 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = bid % tiles;
-  const int rest = bid / tiles;
-  const int fld = rest % 3, pl = rest / 3;
+  const int ntiles = tiles * 3 * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
-  const int n = tile * NF + f;
-  const bool valid = n < d.mt;
-  const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
-  typename FF::In v0;
-  typename FF::Out vo;
-#pragma unroll
-  for (int k = 0; k < FF::PER0; ++k)
-#pragma unroll
-    for (int q = 0; q < FF::R0; ++q)
-      v0[k][q] = (valid && FF::in_valid(t, k)) ? src[(int64_t)FF::in_index(t, k, q) * d.mt] : C2<T>{T(0), T(0)};
-  FF::template run<NF>(v0, vo, buf, buf, W, t, f);
-  if (!valid) return;
-  cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S + n;
   const int h = d.half;
+  TileWalk tw(ntiles);
+  auto load = [&](int id, typename FF::In& v) {
+    const int tile = id % tiles, rest = id / tiles;
+    const int fld = rest % 3, pl = rest / 3;
+    const int n = tile * NF + f;
+    const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
 #pragma unroll
-  for (int k = 0; k < FF::PERN; ++k)
-    if (FF::out_valid(t, k))
+    for (int k = 0; k < FF::PER0; ++k)
 #pragma unroll
-      for (int s2 = 0; s2 < FF::RN; ++s2) {
-        const int e = FF::out_index(t, k, s2);
-        int sl = -1;
-        if (e < h) sl = e;
-        else if (e > L - h) sl = d.mz - (L - e);
-        if (sl >= 0) {
-          const C2<T> x = vo[k][s2];
-          dst[(int64_t)sl * d.mt] = cd{double(x.x) * scale, double(x.y) * scale};
-        }
-      }
-  if (t == 0) dst[(int64_t)h * d.mt] = cd{0.0, 0.0};
+      for (int q = 0; q < FF::R0; ++q)
+        v[k][q] = (n < d.mt && FF::in_valid(t, k)) ? src[(int64_t)FF::in_index(t, k, q) * d.mt] : C2<T>{T(0), T(0)};
+  };
+  auto transform_store = [&](int id, typename FF::In& cur) {
+    typename FF::Out vo;
+    FF::template run<NF>(cur, vo, buf, buf, W, t, f);
+    const int tile = id % tiles, rest = id / tiles;
+    const int fld = rest % 3, pl = rest / 3;
+    const int n = tile * NF + f;
+    if (n < d.mt) {
+      cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S + n;
+#pragma unroll
+      for (int k = 0; k < FF::PERN; ++k)
+        if (FF::out_valid(t, k))
+#pragma unroll
+          for (int s2 = 0; s2 < FF::RN; ++s2) {
+            const int e = FF::out_index(t, k, s2);
+            int sl = -1;
+            if (e < h) sl = e;
+            else if (e > L - h) sl = d.mz - (L - e);
+            if (sl >= 0) {
+              const C2<T> x = vo[k][s2];
+              dst[(int64_t)sl * d.mt] = cd{double(x.x) * scale, double(x.y) * scale};
+            }
+          }
+      if (t == 0) dst[(int64_t)h * d.mt] = cd{0.0, 0.0};
+    }
+  };
+  if constexpr (Z::PREFETCH) {
+    typename FF::In cur, nxt;
+    if (tw.first < tw.last) load(tw.first, cur);
+    for (int id = tw.first; id < tw.last; id += tw.per_xcd) {
+      const int idn = id + tw.per_xcd;
+      if (idn < tw.last) load(idn, nxt);
+      transform_store(id, cur);
+#pragma unroll
+      for (int k = 0; k < FF::PER0; ++k)
+#pragma unroll
+        for (int q = 0; q < FF::R0; ++q) cur[k][q] = nxt[k][q];
+    }
+  } else {
+    typename FF::In cur;
+    if (tw.first < tw.last) {
+      load(tw.first, cur);
+      transform_store(tw.first, cur);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -342,6 +411,13 @@ size_t inter_bytes_per_plane(const tc_ctx* c) {
   return (size_t)6 * c->d.pz * c->d.mt * el;
 }
 
+// Workgroups of a z kernel: with prefetching a few per CU (256 CUs), each
+// walking many tiles; without, one per tile.
+static unsigned z_blocks(int64_t ntiles, bool prefetch) {
+  const int64_t cap = prefetch ? 256 * 8 : ntiles;
+  return (unsigned)(ntiles < cap ? ntiles : cap);
+}
+
 template <typename T, int L>
 static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om, const C2<T>* W) {
   using Z = ZShape<T, L>;
@@ -353,8 +429,8 @@ static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd*
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = (unsigned)np * 6u * (unsigned)tiles;
-  hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, u, om,
+  const unsigned blocks = z_blocks((int64_t)np * 6 * tiles, Z::PREFETCH);
+  hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, u, om,
                      reinterpret_cast<C2<T>*>(c->inter), W);
   return hipGetLastError();
 }
@@ -387,9 +463,9 @@ static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, cd* N, const C2<T>* W)
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = (unsigned)np * 3u * (unsigned)tiles;
+  const unsigned blocks = z_blocks((int64_t)np * 3 * tiles, Z::PREFETCH);
   const double scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
-  hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0,
+  hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np,
                      reinterpret_cast<const C2<T>*>(c->inter), N, W, scale);
   return hipGetLastError();
 }

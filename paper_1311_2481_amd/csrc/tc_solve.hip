@@ -242,22 +242,6 @@ hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x)
 }
 
 // ------------------------------------------------------------------ fused predictor-corrector
-// V_r(u) at a wall row: 1/2 (L+ u+ + L- u-), L+- = D2 + D1/r - (a^2+1+-2a)/r^2 - b^2.
-__device__ __forceinline__ cd wall_vr(const double* R, double a, double b, const cd* vp, const cd* vm, int kbeg) {
-  // vp/vm hold u+-/u- at nodes j+k-4 for k = kbeg..kbeg+4 (index k - kbeg)
-  cd acc = cz();
-  for (int t = 0; t < 5; ++t) {
-    const int k = kbeg + t;
-    const double w = R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR];
-    acc = cfma(acc, 0.5 * w, cadd(vp[t], vm[t]));
-  }
-  const int t0 = HW - kbeg;  // index of the row itself
-  const double dsum = -(a * a + 1.0) * R[RC_IR2] - b * b;
-  acc = cfma(acc, 0.5 * dsum, cadd(vp[t0], vm[t0]));
-  acc = cfma(acc, -a * R[RC_IR2], csub(vp[t0], vm[t0]));
-  return acc;
-}
-
 // Sweeps (rows j = 0..M):
 //  1 ascending : Ne = 2 N^i - N^{i-1} (kept in N_prev); RHS of the pressure
 //                Poisson problem; forward sweep of P                      -> y_p   (in p)

@@ -25,7 +25,7 @@ u+- = u_r +- i u_theta; axial slot s holds l = s (s < m_z/2) or s - m_z.
 import numpy as np
 
 __all__ = ["Config", "CONFIGS", "perturbation_coefficients", "initial_state",
-           "random_state", "random_direction"]
+           "random_state", "random_field_torch", "random_direction"]
 
 
 class Config(dict):
@@ -193,6 +193,19 @@ def random_state(shape, seed, hermitian=True):
     if hermitian:
         x[..., 0, 0] = x[..., 0, 0].real
         x[..., m_z - np.arange(1, h), 0] = np.conj(x[..., np.arange(1, h), 0])
+    return x
+
+
+def random_field_torch(shape, seed, device):
+    """Large unstructured complex128 test array drawn on ``device`` with a
+    seeded torch generator (for sizes where NumPy generation is too slow);
+    the empty axial slot (axis -2 midpoint) is zero."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    x = torch.randn(tuple(shape) + (2,), dtype=torch.float64, device=device, generator=g)
+    x = torch.view_as_complex(x) / np.sqrt(2.0)
+    x[..., shape[-2] // 2, :] = 0
     return x
 
 

@@ -127,3 +127,17 @@ def test_rotational_matches_convective_up_to_bernoulli_gradient():
         errs.append(np.abs(diff).max() / np.abs(nl.nonlinear_conv(P, u)).max())
     assert errs[1] < errs[0] / 2 ** 6, errs
     assert errs[1] < 1e-4
+
+
+def test_single_plane_nonlinear_matches_full():
+    # the per-node evaluation (used for sampled parity at full size) is the
+    # same computation restricted to one radial node
+    cfg = dict(tc_inputs.CONFIGS["small"])
+    cfg.update(amp=0.2, envelope="k53")
+    P = oracle.Problem(cfg["n_r"], cfg["m_theta"], cfg["m_z"], cfg["eta"], cfg["Re_i"], cfg["Re_o"], cfg["dt"])
+    u = tc_inputs.initial_state(P.r, cfg)
+    full = oracle.nonlinear_rot(P, u)
+    for j in (0, 2, 15, P.n_r - 1):
+        lo, hi = max(0, j - 4), min(P.n_r - 1, j + 4)
+        Nj = nl.nonlinear_rot_at(P, u[:, lo:hi + 1], j)
+        np.testing.assert_allclose(Nj, full[:, j], rtol=0, atol=1e-12 * np.abs(full).max())
