@@ -83,7 +83,7 @@ typedef struct {
                          >= 3*m_theta - 2 (3/2 rule, Sec. 3.1) and a supported
                          transform length                                     */
   int32_t p_z;        /* dealiased axial grid; 0 -> 3*m_z/2, >= 3*m_z/2 - 2,
-                         must equal p_theta (one transform length per grid)   */
+                         a supported transform length                         */
   double k_theta;     /* fundamental azimuthal wavenumber (L_theta = 2pi/k_theta) */
   double k_z;         /* fundamental axial wavenumber (Gamma = 2pi/k_z)         */
   double alpha;       /* node-map parameter of eq. nodeDist; 0 = Chebyshev limit */
@@ -148,6 +148,13 @@ tc_status tc_helmholtz_solve_transposed(tc_ctx* ctx, tc_solve_kind k, const void
  * N^{i-1}) (9 fields).  The inner product is sum Re(conj(x) y) over every
  * stored coefficient.  adj_in and adj_out must not overlap. */
 tc_status tc_step_adjoint(tc_ctx* ctx, const void* fwd, const void* adj_in, void* adj_out);
+
+/* Gradient of the perturbation kinetic energy E_pert(u) = 1/2 int |u - U_c|^2 dV
+ * (U_c: circular Couette flow of Sec. 5.1; trapezoid rule in r, Parseval in
+ * theta and z) with respect to the stored coefficients of u (3 fields) under
+ * the inner product of tc_step_adjoint, into g (3 fields).  This is the
+ * seed of the reverse sweep for the final-energy objective. */
+tc_status tc_perturbation_energy_gradient(tc_ctx* ctx, const void* u, void* g);
 
 /* Diagnostics of the current state into HOST memory (5 doubles):
  * kinetic energy, perturbation energy (against circular Couette flow),

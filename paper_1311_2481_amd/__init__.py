@@ -41,7 +41,7 @@ class _Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ["tc_init", "tc_destroy", "tc_last_error", "tc_radial_nodes", "tc_set_state", "tc_get_state",
            "tc_get_history", "tc_step", "tc_nonlinear", "tc_helmholtz_solve", "tc_helmholtz_solve_transposed",
-           "tc_step_adjoint", "tc_get_diag", "tc_check_finite", "tc_set_timing", "tc_kernel_time",
+           "tc_step_adjoint", "tc_perturbation_energy_gradient", "tc_get_diag", "tc_check_finite", "tc_set_timing", "tc_kernel_time",
            "tc_memory_bytes"]
 
 
@@ -67,6 +67,7 @@ def load_library(path=LIB_PATH):
     lib.tc_helmholtz_solve.argtypes = [vp, i32, vp, vp]
     lib.tc_helmholtz_solve_transposed.argtypes = [vp, i32, vp, vp]
     lib.tc_step_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.tc_perturbation_energy_gradient.argtypes = [vp, vp, vp]
     lib.tc_get_diag.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.tc_check_finite.argtypes = [vp]
     lib.tc_set_timing.argtypes = [vp, i32]
@@ -170,6 +171,11 @@ class Solver:
         self._check(self.lib.tc_step_adjoint(self.ctx, self._arr(fwd, 6, "fwd"), self._arr(adj_in, 9, "adj_in"),
                                              self._arr(out, 9, "adj_out")))
         return out
+
+    def energy_gradient(self, u, out=None):
+        g = self.empty(3) if out is None else out
+        self._check(self.lib.tc_perturbation_energy_gradient(self.ctx, self._arr(u, 3, "u"), self._arr(g, 3, "g")))
+        return g
 
     def diag(self):
         out = np.zeros(5)

@@ -270,6 +270,40 @@ __global__ void k_slip(Dims d, const cd* __restrict__ u, double* __restrict__ pa
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Gradient of E_pert = 1/2 int |u - U_c|^2 dV (trapezoid rule in r, Parseval
+// in theta and z) with respect to the stored coefficients under
+// <x, y> = sum Re(conj(x) y):  g+- = (A/2) w_j r_j c_n (u+- - U_c+-),
+// g_z = A w_j r_j c_n u_z, A = (2 pi / k_theta)(2 pi / k_z).
+__global__ void k_egrad(const double* __restrict__ rc, Dims d, double C1, double C2, double area,
+                        const cd* __restrict__ u, cd* __restrict__ g) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.S) return;
+  const int s = (int)(idx / d.mt), n = (int)(idx - (int64_t)s * d.mt);
+  const int M = d.n_r - 1;
+  for (int j = 0; j <= M; ++j) {
+    const int64_t o = j * d.S + idx;
+    if (s == d.nyq) {
+      g[o] = g[d.F + o] = g[2 * d.F + o] = cd{0, 0};
+      continue;
+    }
+    const double r = rc[(int64_t)j * RC_N + RC_R];
+    double w = 0.0;
+    if (j > 0) w += 0.5 * (r - rc[(int64_t)(j - 1) * RC_N + RC_R]);
+    if (j < M) w += 0.5 * (rc[(int64_t)(j + 1) * RC_N + RC_R] - r);
+    const double k = area * w * r * (n == 0 ? 1.0 : 2.0);
+    cd p = u[o], m = u[d.F + o];
+    if (s == 0 && n == 0) {
+      const double U = C1 * r + C2 / r;
+      p.y -= U;
+      m.y += U;
+    }
+    const cd z = u[2 * d.F + o];
+    g[o] = cd{0.5 * k * p.x, 0.5 * k * p.y};
+    g[d.F + o] = cd{0.5 * k * m.x, 0.5 * k * m.y};
+    g[2 * d.F + o] = cd{k * z.x, k * z.y};
+  }
+}
+
 __global__ void k_finite(int64_t count, const double* __restrict__ x, int* __restrict__ flag) {
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -608,6 +642,18 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
   return TC_OK;
 }
 
+tc_status tc_perturbation_energy_gradient(tc_ctx* c, const void* u, void* g) {
+  if (!c) return TC_EINVAL;
+  if (!u || !g) return fail(c, TC_EINVAL, "NULL array");
+  const Dims& d = c->d;
+  const double C1 = (d.Re_o - c->eta * d.Re_i) / (1.0 + c->eta);
+  const double C2 = c->eta * (d.Re_i - c->eta * d.Re_o) / ((1.0 - c->eta) * (1.0 - c->eta * c->eta));
+  const double area = (2.0 * M_PI / d.kt) * (2.0 * M_PI / d.kz);
+  hipLaunchKernelGGL(k_egrad, dim3((unsigned)((d.S + 255) / 256)), dim3(256), 0, c->stream, c->rc_dev, d, C1, C2,
+                     area, static_cast<const cd*>(u), static_cast<cd*>(g));
+  return hip_check(c, hipGetLastError(), "tc_perturbation_energy_gradient");
+}
+
 tc_status tc_check_finite(tc_ctx* c) {
   if (!c) return TC_EINVAL;
   int* flag = nullptr;
@@ -656,12 +702,6 @@ tc_status tc_memory_bytes(const tc_ctx* c, uint64_t* out) {
   if (!c || !out) return TC_EINVAL;
   *out = c->bytes;
   return TC_OK;
-}
-
-tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj_in, void* adj_out) {
-  if (!c) return TC_EINVAL;
-  (void)fwd; (void)adj_in; (void)adj_out;
-  return fail(c, TC_EINVAL, "adjoint step not available in this build");
 }
 
 }  // extern "C"

@@ -43,6 +43,17 @@ struct KernelTimer {
   int launches = 0;
 };
 
+// Sources / destinations of the axial transform kernels: nfields fields
+// taken from (or written to) separate spectral arrays, nf_plane fields per
+// radial plane in the transform-layout buffer.  For the forward kernel the
+// output is multiplied by scale (and by Hermitian weights when weights = 1).
+struct ZIo {
+  const C2<double>* src[9];
+  C2<double>* dst[9];
+  int nfields, nf_plane, weights;
+  double scale;
+};
+
 struct Dims {
   int n_r, mt, mz, pt, pz, nyq, half, ndm;
   int64_t S;      // m_z * m_theta (one radial plane of one field)
@@ -100,6 +111,9 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);
 hipError_t launch_zfwd(tc_ctx* c, int plane0, int nplanes, cd* N);
+hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, bool f32);
+hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32);
+hipError_t launch_theta_adj(tc_ctx* c, int nplanes, void* inter);
 bool fft_length_supported(int L);
 size_t inter_bytes_per_plane(const tc_ctx* c);
 

@@ -123,6 +123,16 @@ template <typename T, int L> struct TShape {
   static constexpr size_t LDS = NBUF * (size_t)lds_len<L>() * RPB * sizeof(C2<T>);
 };
 
+// Output weight of the forward z kernel for field fld at azimuthal index n:
+// 1 for the forward nonlinear term; for the adjoint transforms the
+// Hermitian weights c_n (1 at n = 0, 2 above) on the real-field components
+// (fields 4, 5) and c_n / 2 on the complex-pair components (fields 0-3).
+__device__ __forceinline__ double z_out_weight(int weights, int fld, int n) {
+  if (weights == 0) return 1.0;
+  if (fld < 4) return n == 0 ? 0.5 : 1.0;
+  return n == 0 ? 1.0 : 2.0;
+}
+
 // Persistent z kernels: gridDim.x workgroups loop over all column tiles,
 // loading the next tile into registers while the current one is being
 // transformed (the LDS then never waits on memory).  Workgroups on one XCD
@@ -144,9 +154,7 @@ struct TileWalk {
 
 // ------------------------------------------------------------------ z inverse
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, int nplanes,
-                                                                               const cd* __restrict__ u,
-                                                                               const cd* __restrict__ om,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, int nplanes, ZIo io,
                                                                                C2<T>* __restrict__ inter,
                                                                                const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
@@ -155,15 +163,15 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
-  const int ntiles = tiles * 6 * nplanes;
+  const int ntiles = tiles * io.nfields * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int h = d.half;
   TileWalk tw(ntiles);
   auto load = [&](int id, cd (&raw)[FI::PER0][FI::R0]) {
     const int tile = id % tiles, rest = id / tiles;
-    const int fld = rest % 6, pl = rest / 6;
+    const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
-    const cd* src = (fld < 3 ? u + fld * d.F : om + (fld - 3) * d.F) + (int64_t)(plane0 + pl) * d.S + n;
+    const cd* src = io.src[fld] + (int64_t)(plane0 + pl) * d.S + n;
 #pragma unroll
     for (int k = 0; k < FI::PER0; ++k)
 #pragma unroll
@@ -184,10 +192,10 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
       for (int q = 0; q < FI::R0; ++q) v0[k][q] = C2<T>{T(raw[k][q].x), T(raw[k][q].y)};
     FI::template run<NF>(v0, vo, buf, buf, W, t, f);
     const int tile = id % tiles, rest = id / tiles;
-    const int fld = rest % 6, pl = rest / 6;
+    const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
     if (n < d.mt) {
-      C2<T>* dst = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+      C2<T>* dst = inter + ((int64_t)(pl * io.nf_plane + fld) * L) * d.mt + n;
 #pragma unroll
       for (int k = 0; k < FI::PERN; ++k)
         if (FI::out_valid(t, k))
@@ -322,28 +330,158 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
   }
 }
 
+// ------------------------------------------------------------------ theta pass, adjoint
+// Transposed nonlinear term (used by the discrete adjoint step), per z-row
+// of the transform-layout buffer holding 9 fields per plane: the forward
+// fields (u+, u-, u_z, omega+, omega-, omega_z) and the cotangent of N
+// (N+, N-, N_z) after the axial inverse transform.  The transpose of the
+// forward transform (1/P, truncation, Hermitian half spectrum) is an
+// inverse transform of the cotangent with weight 1 on every stored mode:
+// h_g = g_r + i g_theta has spectrum N+ (n > 0), conj(N-(|n|)) (n < 0),
+// N+ + conj(N-) (n = 0), and g_z is the real part of the one-sided sum of
+// N_z.  Then omega_bar = u x g and u_bar = g x omega pointwise, and the
+// forward transforms of u_bar_r + i u_bar_theta, omega_bar_r + i
+// omega_bar_theta and u_bar_z + i omega_bar_z give (after the axial pass with
+// Hermitian weights) the cotangents of u+-, omega+-, u_z, omega_z.  The six
+// results overwrite fields 0-5 of the row.
+template <typename T, int L>
+__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_theta_adj(Dims d, int nplanes,
+                                                                                     C2<T>* __restrict__ inter,
+                                                                                     const C2<T>* __restrict__ W) {
+  using TS = TShape<T, L>;
+  constexpr int TPF = TS::TPF, RPB = TS::RPB;
+  using FI = Fft<T, L, TPF, +1, false>;
+  using FF = Fft<T, L, TPF, -1, true>;
+  extern __shared__ unsigned char lds_raw[];
+  C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
+  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L>() * RPB : bufa;
+  const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
+  const int64_t rows = (int64_t)nplanes * d.pz;
+  const int64_t row = (int64_t)blockIdx.x * RPB + f;
+  const bool valid = row < rows;
+  const int pl = valid ? (int)(row / d.pz) : 0;
+  const int z = valid ? (int)(row - (int64_t)pl * d.pz) : 0;
+  const int64_t fstride = (int64_t)d.pz * d.mt;
+  C2<T>* base = inter + (int64_t)pl * 9 * fstride + (int64_t)z * d.mt;
+  const int mt = d.mt;
+  auto fld = [&](int k) { return base + (int64_t)k * fstride; };
+  // mode: 0 pair (n = 0 averaged), 1 packed real pair, 2 pair (n = 0 summed), 3 one-sided
+  auto spec = [&](int mode, const C2<T>* A, const C2<T>* B, int e) -> C2<T> {
+    const int nn = (e <= L / 2) ? e : e - L;
+    C2<T> v = {T(0), T(0)};
+    if (!valid) return v;
+    if (mode == 0 || mode == 2) {
+      if (nn > 0 && nn < mt) v = A[nn];
+      else if (nn < 0 && -nn < mt) v = cconj(B[-nn]);
+      else if (nn == 0) {
+        const C2<T> p0 = A[0], m0 = B[0];
+        const T w = mode == 0 ? T(0.5) : T(1);
+        v = {w * (p0.x + m0.x), w * (p0.y - m0.y)};
+      }
+    } else if (mode == 1) {
+      if (nn > 0 && nn < mt) {
+        const C2<T> x = A[nn], y = B[nn];
+        v = {x.x - y.y, x.y + y.x};
+      } else if (nn < 0 && -nn < mt) {
+        const C2<T> x = cconj(A[-nn]), y = cconj(B[-nn]);
+        v = {x.x - y.y, x.y + y.x};
+      } else if (nn == 0) {
+        v = {A[0].x, B[0].x};
+      }
+    } else {
+      if (nn >= 0 && nn < mt) v = A[nn];
+    }
+    return v;
+  };
+  typename FI::In v0;
+  auto inverse = [&](int mode, const C2<T>* A, const C2<T>* B, typename FI::Out& out) {
+#pragma unroll
+    for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+      for (int q = 0; q < FI::R0; ++q)
+        v0[k][q] = FI::in_valid(t, k) ? spec(mode, A, B, FI::in_index(t, k, q)) : C2<T>{T(0), T(0)};
+    FI::template run<RPB>(v0, out, bufa, bufb, W, t, f);
+  };
+  typename FI::Out hu, hw, g, hg, gz;
+  inverse(0, fld(0), fld(1), hu);
+  inverse(0, fld(3), fld(4), hw);
+  inverse(1, fld(2), fld(5), g);
+  inverse(2, fld(6), fld(7), hg);
+  inverse(3, fld(8), fld(8), gz);
+  typename FF::In a1, a2, a3;
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T ur = hu[k][q].x, ut = hu[k][q].y, uz = g[k][q].x;
+      const T wr = hw[k][q].x, wt = hw[k][q].y, wz = g[k][q].y;
+      const T gr = hg[k][q].x, gt = hg[k][q].y, gzv = gz[k][q].x;
+      // u_bar = g x omega, omega_bar = u x g
+      a1[k][q] = {gt * wz - gzv * wt, gzv * wr - gr * wz};
+      a2[k][q] = {ut * gzv - uz * gt, uz * gr - ur * gzv};
+      a3[k][q] = {gr * wt - gt * wr, ur * gt - ut * gr};
+    }
+  typename FF::Out o;
+  auto store_pair = [&](int fa, int fb) {
+    if (!valid) return;
+    C2<T>* Bp = fld(fa);
+    C2<T>* Bm = fld(fb);
+#pragma unroll
+    for (int k = 0; k < FF::PERN; ++k)
+      if (FF::out_valid(t, k))
+#pragma unroll
+        for (int s2 = 0; s2 < FF::RN; ++s2) {
+          const int e = FF::out_index(t, k, s2);
+          if (e < mt) Bp[e] = o[k][s2];
+          if (e == 0) Bm[0] = cconj(o[k][s2]);
+          else if (L - e < mt) Bm[L - e] = cconj(o[k][s2]);
+        }
+  };
+  FF::template run<RPB>(a1, o, bufa, bufb, W, t, f);
+  store_pair(0, 1);
+  FF::template run<RPB>(a2, o, bufa, bufb, W, t, f);
+  store_pair(2, 3);
+  FF::template run<RPB>(a3, o, bufa, bufb, W, t, f);
+  // separate the packed real fields: X(n) = (G(n) + conj G(-n))/2, Y(n) = (G(n) - conj G(-n))/(2i)
+  // G(n) and G(-n) sit in different threads: go through LDS
+#pragma unroll
+  for (int k = 0; k < FF::PERN; ++k)
+    if (FF::out_valid(t, k))
+#pragma unroll
+      for (int s2 = 0; s2 < FF::RN; ++s2) bufa[lds_pad(FF::out_index(t, k, s2)) * RPB + f] = o[k][s2];
+  __syncthreads();
+  if (valid) {
+    C2<T>* X = fld(4);
+    C2<T>* Y = fld(5);
+    for (int nn = t; nn < mt; nn += TPF) {
+      const C2<T> gp = bufa[lds_pad(nn) * RPB + f];
+      const C2<T> gm = cconj(bufa[lds_pad((L - nn) % L) * RPB + f]);
+      X[nn] = {T(0.5) * (gp.x + gm.x), T(0.5) * (gp.y + gm.y)};
+      Y[nn] = {T(0.5) * (gp.y - gm.y), T(-0.5) * (gp.x - gm.x)};
+    }
+  }
+}
+
 // ------------------------------------------------------------------ z forward
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0, int nplanes,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0, int nplanes, ZIo io,
                                                                                const C2<T>* __restrict__ inter,
-                                                                               cd* __restrict__ N,
-                                                                               const C2<T>* __restrict__ W,
-                                                                               double scale) {
+                                                                               const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
   constexpr int NF = Z::NF, TPF = Z::TPF;
   using FF = Fft<T, L, TPF, -1, false>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
-  const int ntiles = tiles * 3 * nplanes;
+  const int ntiles = tiles * io.nfields * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int h = d.half;
   TileWalk tw(ntiles);
   auto load = [&](int id, typename FF::In& v) {
     const int tile = id % tiles, rest = id / tiles;
-    const int fld = rest % 3, pl = rest / 3;
+    const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
-    const C2<T>* src = inter + ((int64_t)(pl * 6 + fld) * L) * d.mt + n;
+    const C2<T>* src = inter + ((int64_t)(pl * io.nf_plane + fld) * L) * d.mt + n;
 #pragma unroll
     for (int k = 0; k < FF::PER0; ++k)
 #pragma unroll
@@ -354,10 +492,11 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
     typename FF::Out vo;
     FF::template run<NF>(cur, vo, buf, buf, W, t, f);
     const int tile = id % tiles, rest = id / tiles;
-    const int fld = rest % 3, pl = rest / 3;
+    const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
     if (n < d.mt) {
-      cd* dst = N + fld * d.F + (int64_t)(plane0 + pl) * d.S + n;
+      cd* dst = io.dst[fld] + (int64_t)(plane0 + pl) * d.S + n;
+      const double scale = io.scale * z_out_weight(io.weights, fld, n);
 #pragma unroll
       for (int k = 0; k < FF::PERN; ++k)
         if (FF::out_valid(t, k))
@@ -419,7 +558,7 @@ static unsigned z_blocks(int64_t ntiles, bool prefetch) {
 }
 
 template <typename T, int L>
-static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om, const C2<T>* W) {
+static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, const C2<T>* W) {
   using Z = ZShape<T, L>;
   const size_t lds = Z::LDS;
   static bool attr = false;
@@ -429,9 +568,9 @@ static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd*
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = z_blocks((int64_t)np * 6 * tiles, Z::PREFETCH);
-  hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, u, om,
-                     reinterpret_cast<C2<T>*>(c->inter), W);
+  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles, Z::PREFETCH);
+  hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, io,
+                     reinterpret_cast<C2<T>*>(inter), W);
   return hipGetLastError();
 }
 
@@ -453,7 +592,7 @@ static hipError_t run_theta(tc_ctx* c, int np, const C2<T>* W) {
 }
 
 template <typename T, int L>
-static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, cd* N, const C2<T>* W) {
+static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, const C2<T>* W) {
   using Z = ZShape<T, L>;
   const size_t lds = Z::LDS;
   static bool attr = false;
@@ -463,18 +602,27 @@ static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, cd* N, const C2<T>* W)
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = z_blocks((int64_t)np * 3 * tiles, Z::PREFETCH);
-  const double scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
-  hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np,
-                     reinterpret_cast<const C2<T>*>(c->inter), N, W, scale);
+  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles, Z::PREFETCH);
+  hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, io,
+                     reinterpret_cast<const C2<T>*>(inter), W);
   return hipGetLastError();
 }
 
 hipError_t launch_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om) {
-  const bool f32 = c->g.precision == TC_FP32_BULK;
-#define TC_CASE(LL)                                                                   \
-  if (c->d.pz == LL) return f32 ? run_zinv<float, LL>(c, plane0, np, u, om, c->twf_z) \
-                                : run_zinv<double, LL>(c, plane0, np, u, om, c->tw_z);
+  ZIo io{};
+  for (int k = 0; k < 3; ++k) {
+    io.src[k] = u + k * c->d.F;
+    io.src[3 + k] = om + k * c->d.F;
+  }
+  io.nfields = 6;
+  io.nf_plane = 6;
+  return launch_zinv_io(c, plane0, np, io, c->inter, c->g.precision == TC_FP32_BULK);
+}
+
+hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, bool f32) {
+#define TC_CASE(LL)                                                                        \
+  if (c->d.pz == LL) return f32 ? run_zinv<float, LL>(c, plane0, np, io, inter, c->twf_z) \
+                                : run_zinv<double, LL>(c, plane0, np, io, inter, c->tw_z);
   TC_FFT_LENGTHS(TC_CASE)
 #undef TC_CASE
   return hipErrorInvalidValue;
@@ -489,10 +637,45 @@ hipError_t launch_theta(tc_ctx* c, int np) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_zfwd(tc_ctx* c, int plane0, int np, cd* N) {
-  const bool f32 = c->g.precision == TC_FP32_BULK;
+template <int L>
+static hipError_t run_theta_adj(tc_ctx* c, int np, void* inter) {
+  using TS = TShape<double, L>;
+  const size_t lds = TS::LDS;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_theta_adj<double, L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  const int64_t rows = (int64_t)np * c->d.pz;
+  const unsigned blocks = (unsigned)((rows + TS::RPB - 1) / TS::RPB);
+  hipLaunchKernelGGL((k_theta_adj<double, L>), dim3(blocks), dim3(TS::TPF * TS::RPB), lds, c->stream, c->d, np,
+                     reinterpret_cast<cd*>(inter), c->tw_t);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_adj(tc_ctx* c, int np, void* inter) {
 #define TC_CASE(LL) \
-  if (c->d.pz == LL) return f32 ? run_zfwd<float, LL>(c, plane0, np, N, c->twf_z) : run_zfwd<double, LL>(c, plane0, np, N, c->tw_z);
+  if (c->d.pt == LL) return run_theta_adj<LL>(c, np, inter);
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_zfwd(tc_ctx* c, int plane0, int np, cd* N) {
+  ZIo io{};
+  for (int k = 0; k < 3; ++k) io.dst[k] = N + k * c->d.F;
+  io.nfields = 3;
+  io.nf_plane = 6;
+  io.scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
+  io.weights = 0;
+  return launch_zfwd_io(c, plane0, np, io, c->inter, c->g.precision == TC_FP32_BULK);
+}
+
+hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32) {
+#define TC_CASE(LL)                                                                       \
+  if (c->d.pz == LL) return f32 ? run_zfwd<float, LL>(c, plane0, np, io, inter, c->twf_z) \
+                                : run_zfwd<double, LL>(c, plane0, np, io, inter, c->tw_z);
   TC_FFT_LENGTHS(TC_CASE)
 #undef TC_CASE
   return hipErrorInvalidValue;
