@@ -52,9 +52,27 @@ def kernel_bytes(cfg, precision):
     }
 
 
+KERNEL_SOURCES = {
+    "pc": ["tc_solve.hip", "tc_internal.h"],
+    "curl": ["tc_nonlinear.hip", "tc_internal.h"],
+    "zinv": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
+    "theta": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
+    "zfwd": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
+}
+KERNEL_LAUNCHES = {"pc": "k_pc1 + k_pc2 + k_pc3 + k_pc4 (one launch each per step)", "curl": "k_curl",
+                   "zinv": "k_zinv", "theta": "k_theta", "zfwd": "k_zfwd"}
+
+
+def source_digest(kernel):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1311_2481_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def read_traffic(kernel, workload, precision):
-    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
@@ -63,8 +81,7 @@ def read_traffic(kernel, workload, precision):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1311_2481_amd", "csrc", vals.get("source", ""))
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != vals.get("source_sha"):
+    if vals.get("source_sha") != source_digest(kernel):
         return None
     try:
         return float(vals["bytes_per_launch"])
@@ -94,6 +111,54 @@ def run_gpu(cfg, precision, steps, warmup, u0):
     del S
     torch.cuda.empty_cache()
     return dict(seconds=dt, times=times, finite=finite, diag=diag, mem=mem)
+
+
+def adjoint_ratio(repeats=3):
+    """Cost of the gradient of the final perturbation energy (differentiation
+    workload: forward with checkpoints + reverse sweep with segment
+    recompute) over a plain forward run of the same T steps."""
+    import torch
+    import tc_inputs
+    from paper_1311_2481_amd import Solver
+    from paper_1311_2481_amd.autograd import final_energy_and_gradient
+    cfg = tc_inputs.Config(tc_inputs.CONFIGS["adjoint"])
+    S = Solver(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
+               k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha)
+    r = S.radial_nodes()
+    u0 = tc_inputs.initial_state(r, cfg, device="cuda")
+    pert = tc_inputs.initial_state(r, cfg, device="cuda", with_couette=False)
+    base = u0 - pert
+    T, every = cfg.steps, cfg.checkpoint_every
+
+    def timed(fn):
+        ts = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    def forward():
+        S.set_state(u0)
+        S.step(T)
+
+    forward()
+    t_fwd = timed(forward)
+    final_energy_and_gradient(S, base, pert, T, every=every)
+    t_grad = timed(lambda: final_energy_and_gradient(S, base, pert, T, every=every))
+    # one adjoint step alone, against one forward step
+    fwd = torch.cat([u0, u0], 0)
+    adj_in = tc_inputs.random_field_torch((9,) + tuple(u0.shape[1:]), 7, "cuda")
+    n = 50
+    t_adj = timed(lambda: [S.step_adjoint(fwd, adj_in) for _ in range(n)]) / n
+    S.close()
+    return {"value": round(t_grad / t_fwd, 3), "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4),
+            "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_fwd / T * 1e3, 4),
+            "workload": (f"eta={cfg.eta}, Re_i={cfg.Re_i:g}, Re_o={cfg.Re_o:g}, N_r={cfg.n_r}, "
+                         f"{2 * cfg.m_theta}x{cfg.m_z} physical, FP64, T={T} steps, dt={cfg.dt:g}, "
+                         f"checkpoint every {every}; median of {repeats}")}
 
 
 def cpu_baseline(cfg, u0_dev, repeats=3):
@@ -147,6 +212,7 @@ def main():
     ap.add_argument("--workload", default="production")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -186,14 +252,18 @@ def main():
     sps = args.steps / f64["seconds"]
     kb = kernel_bytes(cfg, "fp64")
     per_step = {k: v[0] * max(v[1], 1) / args.steps for k, v in f64["times"].items()}
+    kernels = {}
+    for k, (ms, nl) in f64["times"].items():
+        alg = kb[k] / (nl / args.steps)
+        ach = alg / (ms * 1e-3) / 1e9
+        kernels[k] = {"launches": KERNEL_LAUNCHES[k], "mean_launch_ms": round(ms, 4),
+                      "algorithmic_bytes_per_launch": int(alg), "achieved_GBs": round(ach, 1),
+                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": read_traffic(k, args.workload, "fp64")}
     dom = max(per_step, key=per_step.get)
-    ms, nl = f64["times"][dom]
-    launches_per_step = nl / args.steps
-    alg = kb[dom] / launches_per_step
-    achieved = alg / (ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, args.workload, "fp64"),
-            "algorithmic_bytes_per_launch": int(alg), "mean_launch_ms": round(ms, 4)}
+    kd = kernels[dom]
+    roof = {"kernel": dom, "launches": kd["launches"], "bound": "hbm", "achieved": kd["achieved_GBs"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"], "traffic": kd["traffic"],
+            "algorithmic_bytes_per_launch": kd["algorithmic_bytes_per_launch"], "mean_launch_ms": kd["mean_launch_ms"]}
     out = {
         "metric": METRIC, "value": round(sps, 4), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 / sps, 3), "higher_is_better": True, "scaling": "weak",
@@ -204,6 +274,7 @@ def main():
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
         "roofline": roof,
+        "kernels": kernels,
     }
     if f32:
         s32 = args.steps / f32["seconds"]
@@ -213,6 +284,9 @@ def main():
                             "kernels_ms_per_step": {k: round(v[0] * max(v[1], 1) / args.steps, 4)
                                                     for k, v in f32["times"].items()}}
     out["adjoint_forward_ratio"] = None
+    if not args.no_adjoint:
+        print("[bench] adjoint/forward cost ratio", file=sys.stderr, flush=True)
+        out["adjoint_forward_ratio"] = adjoint_ratio()
     if not args.no_cpu:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, u0)
