@@ -141,3 +141,50 @@ def test_single_plane_nonlinear_matches_full():
         lo, hi = max(0, j - 4), min(P.n_r - 1, j + 4)
         Nj = nl.nonlinear_rot_at(P, u[:, lo:hi + 1], j)
         np.testing.assert_allclose(Nj, full[:, j], rtol=0, atol=1e-12 * np.abs(full).max())
+
+
+def test_energy_matches_physical_space_quadrature():
+    """Kinetic energy from the spectral formula (Parseval with c_n weights,
+    +- components) equals 1/2 sum_j w_j r_j * mean over an explicit (theta, z)
+    grid of u_r^2 + u_theta^2 + u_z^2 times the box area, with the physical
+    values summed term by term from the coefficients."""
+    from oracle import diagnostics as dg
+    P = _tiny(m_theta=3, m_z=4, n_r=7)
+    u = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), 21)
+    # u_r = (u+ + u-)/2, u_theta = -i (u+ - u-)/2 are real fields: their
+    # coefficients must obey the n = 0 symmetry for the comparison to hold
+    up, um = u[0].copy(), u[1].copy()
+    ur_c, ut_c = (up + um) / 2, -0.5j * (up - um)
+    for c in (ur_c, ut_c):
+        for s in range(1, P.m_z):
+            if s != P.nyq:
+                c[:, P.m_z - s, 0] = np.conj(c[:, s, 0])
+        c[:, 0, 0] = c[:, 0, 0].real
+    u = np.stack([ur_c + 1j * ut_c, ur_c - 1j * ut_c, u[2]])
+    nt, nz = 2 * P.m_theta + 1, P.m_z + 1          # enough points for exact quadrature of squares
+    th = 2 * np.pi / P.k_theta * np.arange(nt) / nt
+    z = 2 * np.pi / P.k_z * np.arange(nz) / nz
+
+    def values(c):
+        g = np.zeros((P.n_r, nz, nt))
+        spec = {}
+        for s in range(P.m_z):
+            if s == P.nyq:
+                continue
+            for n in range(P.m_theta):
+                spec[(int(P.l[s]), n)] = c[:, s, n]
+        for (l, n), v in spec.items():
+            ph = np.exp(1j * (n * P.k_theta * th[None, :] + l * P.k_z * z[:, None]))
+            term = v[:, None, None] * ph[None]
+            g += term.real if n == 0 else 2 * term.real
+        return g
+
+    comp = [values(ur_c), values(ut_c), values(u[2])]
+    ms = sum((g ** 2).mean(axis=(1, 2)) for g in comp)
+    area = (2 * np.pi / P.k_theta) * (2 * np.pi / P.k_z)
+    w = np.zeros(P.n_r)
+    h = np.diff(P.r)
+    w[:-1] += h / 2
+    w[1:] += h / 2
+    ref = 0.5 * area * np.sum(w * P.r * ms)
+    assert abs(dg.energy(P, u) - ref) <= 1e-13 * ref
