@@ -16,9 +16,10 @@
 // and the nonlinear term's adjoint (transposed transforms, see the azimuthal
 // adjoint kernel) applied to N_bar_total = 2 Ne_bar + N_bar.
 //
-// Work decomposition: one lane per stored mode (s, n) walking the radial
-// nodes; D1^T is applied by gathering the (up to 9) rows whose stencils
-// touch a node.  The banded transposed solves reuse the solve kernel.
+// Work decomposition: one thread per (radial node, stored mode) point on a
+// 2-D grid (x: mode slot, y: node); D1^T is applied by gathering the (up to
+// 9) rows whose stencils touch a node, from fields written by an earlier
+// launch.  The banded transposed solves reuse the solve kernels.
 #include "tc_internal.h"
 
 namespace tc {
@@ -32,6 +33,7 @@ __device__ __forceinline__ cd cpl(cd a, cd b) { return cd{a.x + b.x, a.y + b.y};
 __device__ __forceinline__ cd cmi(cd a, cd b) { return cd{a.x - b.x, a.y - b.y}; }
 
 struct Slot {
+  int k;        // radial node
   int64_t idx;  // s * m_theta + n
   int s, n;
   double a, b;
@@ -40,6 +42,7 @@ struct Slot {
 
 __device__ __forceinline__ bool make_slot(const Dims& d, Slot& q) {
   q.idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  q.k = blockIdx.y;
   if (q.idx >= d.S) return false;
   q.s = (int)(q.idx / d.mt);
   q.n = (int)(q.idx - (int64_t)q.s * d.mt);
@@ -83,7 +86,8 @@ __global__ void k_adj_phi(const double* __restrict__ rc, Dims d, const cd* __res
                           cd* __restrict__ out, int pass) {
   Slot q;
   if (!make_slot(d, q)) return;
-  for (int k = 0; k < d.n_r; ++k) {
+  {
+    const int k = q.k;
     const int64_t o = k * d.S + q.idx;
     if (pass == 0) {
       vsum[o] = q.nyq ? cz() : cpl(ub[o], ub[d.F + o]);
@@ -101,15 +105,16 @@ __global__ void k_adj_ustar(const double* __restrict__ rc, Dims d, const cd* __r
   Slot q;
   if (!make_slot(d, q)) return;
   const int M = d.n_r - 1;
-  for (int k = 0; k <= M; ++k) {
+  {
+    const int k = q.k;
     const int64_t o = k * d.S + q.idx;
     if (pass == 0) {
       mr[o] = (k == 0 || k == M || q.nyq) ? cz() : r[o];
-      continue;
+      return;
     }
     if (q.nyq) {
       us[o] = us[d.F + o] = us[2 * d.F + o] = cz();
-      continue;
+      return;
     }
     const double ir = rc[(int64_t)k * RC_N + RC_IR];
     const cd f = mr[o];
@@ -128,14 +133,15 @@ __global__ void k_adj_rhsu(const double* __restrict__ rc, Dims d, cd* __restrict
   Slot q;
   if (!make_slot(d, q)) return;
   const int M = d.n_r - 1;
-  for (int k = 0; k <= M; ++k) {
+  {
+    const int k = q.k;
     const int64_t o = k * d.S + q.idx;
     if (pass == 0) {
       const bool z = (k == 0 || k == M || q.nyq);
       for (int c = 0; c < 3; ++c)
         if (z) ru[c * d.F + o] = cz();
       vsum[o] = z ? cz() : cpl(ru[o], ru[d.F + o]);
-      continue;
+      return;
     }
     for (int c = 0; c < 3; ++c) {
       const cd r = ru[c * d.F + o];
@@ -157,13 +163,14 @@ __global__ void k_adj_rhsp(const double* __restrict__ rc, Dims d, const cd* __re
   Slot q;
   if (!make_slot(d, q)) return;
   const int M = d.n_r - 1;
-  for (int k = 0; k <= M; ++k) {
+  {
+    const int k = q.k;
     const int64_t o = k * d.S + q.idx;
     if (pass == 0) {
       const bool wall = (k == 0 || k == M) && !(k == M && q.zero_mode);
       mr[o] = (k == 0 || k == M || q.nyq) ? cz() : rp[o];
       wr[o] = (wall && !q.nyq) ? rp[o] : cz();
-      continue;
+      return;
     }
     const double ir = rc[(int64_t)k * RC_N + RC_IR];
     const double ir2 = rc[(int64_t)k * RC_N + RC_IR2];
@@ -227,15 +234,16 @@ __global__ void k_adj_curl(const double* __restrict__ rc, Dims d, const cd* __re
   const cd* om = nl + 3 * F;
   const cd* uzd = nl + 4 * F;
   const cd* oz = nl + 5 * F;
-  for (int k = 0; k < d.n_r; ++k) {
+  {
+    const int k = q.k;
     const int64_t o = k * d.S + q.idx;
     if (pass == 0) {
       od[o] = q.nyq ? cz() : cmi(op[o], om[o]);
-      continue;
+      return;
     }
     if (q.nyq) {
       out[o] = out[F + o] = out[2 * F + o] = cz();
-      continue;
+      return;
     }
     const double ir = rc[(int64_t)k * RC_N + RC_IR];
     const cd dz = d1t(rc, d, oz, q.idx, k, RC_W1);
@@ -309,7 +317,7 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   cd* out_up = out + 3 * F;
   cd* out_np = out + 6 * F;
 
-  const dim3 blk(256), grd((unsigned)((d.S + 255) / 256));
+  const dim3 blk(256), grd((unsigned)((d.S + 255) / 256), (unsigned)d.n_r);
   hipStream_t st = c->stream;
   hipError_t e;
 #define TC_TRY(x) \
@@ -321,16 +329,16 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   hipLaunchKernelGGL(k_adj_phi, grd, blk, 0, st, c->rc_dev, d, ubn, vsum, phib, 0);
   hipLaunchKernelGGL(k_adj_phi, grd, blk, 0, st, c->rc_dev, d, ubn, vsum, phib, 1);
   TC_TRY(hipGetLastError());
-  TC_TRY(launch_solve(c, OP_P, 1, phib, rphi));
+  TC_TRY(launch_solve_t(c, OP_P, 1, phib, rphi));
   hipLaunchKernelGGL(k_adj_ustar, grd, blk, 0, st, c->rc_dev, d, ubn, rphi, mr, us, 0);
   hipLaunchKernelGGL(k_adj_ustar, grd, blk, 0, st, c->rc_dev, d, ubn, rphi, mr, us, 1);
   TC_TRY(hipGetLastError());
-  for (int k = 0; k < 3; ++k) TC_TRY(launch_solve(c, OP_HP + k, 1, us + k * F, ru + k * F));
+  TC_TRY(launch_solve_t(c, OP_HP, 3, us, ru));
   hipLaunchKernelGGL(k_adj_rhsu, grd, blk, 0, st, c->rc_dev, d, ru, vsum, out_u, out_up, neb, pb, 0);
   hipLaunchKernelGGL(k_adj_rhsu, grd, blk, 0, st, c->rc_dev, d, ru, vsum, out_u, out_up, neb, pb, 1);
   TC_TRY(hipGetLastError());
   // pressure predictor, transposed
-  TC_TRY(launch_solve(c, OP_P, 1, pb, rp));
+  TC_TRY(launch_solve_t(c, OP_P, 1, pb, rp));
   hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, mr, wr, neb, out_u, out_up, nin, out_np, ntot, 0);
   hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, mr, wr, neb, out_u, out_up, nin, out_np, ntot, 1);
   TC_TRY(hipGetLastError());

@@ -143,10 +143,65 @@ constexpr RadixList reversed(RadixList rl) {
   return o;
 }
 
-__host__ __device__ constexpr int lds_pad(int e) { return e + (e >> 3); }
-template <int L> __host__ __device__ constexpr int lds_len() { return lds_pad(L - 1) + 1; }
+// LDS slot of element e.  SWZ = false: one pad word every 8 elements.
+// SWZ = true (lengths that are multiples of 16): no padding; the slots of
+// each 16-element block are permuted by bits 3-6 and 9-12 of e, which
+// removes the bank conflicts of the strided exchanges at the cost of a few
+// integer operations per access.
+template <int L, bool SWZ> __host__ __device__ constexpr int lds_slot(int e) {
+  if constexpr (SWZ) {
+    static_assert(L % 16 == 0, "swizzled layout needs L % 16 == 0");
+    return (e & ~15) | ((e ^ (e >> 3) ^ (e >> 9)) & 15);
+  } else {
+    return e + (e >> 3);
+  }
+}
+template <int L, bool SWZ> __host__ __device__ constexpr int lds_len() {
+  if constexpr (SWZ) return L;
+  else return lds_slot<L, false>(L - 1) + 1;
+}
 
-template <typename T, int L, int TPF, int SIGN, bool REV>
+// Twiddles w^q, q = 1..R-1, of one butterfly, w = W[base] (conjugated for
+// SIGN > 0).  With TC_TW_DERIVE only w, w^2 (and w^4 for radix 8) are
+// loaded and the other powers formed by complex products (a few ulp).
+#ifndef TC_TW_DERIVE
+#define TC_TW_DERIVE 1
+#endif
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void twiddles(const C2<T>* __restrict__ W, int base, C2<T>* w) {
+  auto ld = [&](int q) {
+    C2<T> x = W[q * base];
+    if (SIGN > 0) x.y = -x.y;
+    return x;
+  };
+  if constexpr (!TC_TW_DERIVE || R == 2) {
+#pragma unroll
+    for (int q = 1; q < R; ++q) w[q] = ld(q);
+  } else if constexpr (R == 3) {
+    w[1] = ld(1);
+    w[2] = cmul(w[1], w[1]);
+  } else if constexpr (R == 4) {
+    w[1] = ld(1);
+    w[2] = ld(2);
+    w[3] = cmul(w[1], w[2]);
+  } else if constexpr (R == 5) {
+    w[1] = ld(1);
+    w[2] = ld(2);
+    w[3] = cmul(w[1], w[2]);
+    w[4] = cmul(w[2], w[2]);
+  } else {
+    static_assert(R == 8, "radix");
+    w[1] = ld(1);
+    w[2] = ld(2);
+    w[4] = ld(4);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[1], w[4]);
+    w[6] = cmul(w[2], w[4]);
+    w[7] = cmul(w[3], w[4]);
+  }
+}
+
+template <typename T, int L, int TPF, int SIGN, bool REV, bool SWZ = false>
 struct Fft {
   static constexpr RadixList RL = REV ? reversed(make_radices(L)) : make_radices(L);
   static_assert(RL.n > 0, "unsupported transform length");
@@ -172,7 +227,7 @@ struct Fft {
       const int j = t + k * TPF;
       if (NB % TPF == 0 || j < NB) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[k][q] = src[lds_pad(j + q * NB) * NF + f];
+        for (int q = 0; q < R; ++q) v[k][q] = src[lds_slot<L, SWZ>(j + q * NB) * NF + f];
       }
     }
     if (inplace) __syncthreads();
@@ -181,16 +236,14 @@ struct Fft {
       const int j = t + k * TPF;
       if (NB % TPF == 0 || j < NB) {
         const int kk = j % NS;
+        C2<T> w[R];
+        twiddles<R, SIGN, T>(W, kk * (L / (NS * R)), w);  // q kk L/(NS R) < L
 #pragma unroll
-        for (int q = 1; q < R; ++q) {
-          C2<T> w = W[(q * kk * (L / (NS * R))) % L];
-          if (SIGN > 0) w.y = -w.y;
-          v[k][q] = cmul(v[k][q], w);
-        }
+        for (int q = 1; q < R; ++q) v[k][q] = cmul(v[k][q], w[q]);
         Butterfly<R, SIGN, T>::run(v[k]);
         const int base = (j / NS) * NS * R + kk;
 #pragma unroll
-        for (int s = 0; s < R; ++s) dst[lds_pad(base + s * NS) * NF + f] = v[k][s];
+        for (int s = 0; s < R; ++s) dst[lds_slot<L, SWZ>(base + s * NS) * NF + f] = v[k][s];
       }
     }
     __syncthreads();
@@ -233,7 +286,7 @@ struct Fft {
           if (NB % TPF == 0 || j < NB) {
             Butterfly<R0, SIGN, T>::run(v0[k]);
 #pragma unroll
-            for (int s = 0; s < R0; ++s) a[lds_pad(j * R0 + s) * NF + f] = v0[k][s];
+            for (int s = 0; s < R0; ++s) a[lds_slot<L, SWZ>(j * R0 + s) * NF + f] = v0[k][s];
           }
         }
         __syncthreads();
@@ -249,13 +302,11 @@ struct Fft {
           const int j = t + k * TPF;
           if (NB % TPF == 0 || j < NB) {
 #pragma unroll
-            for (int q = 0; q < RN; ++q) vn[k][q] = src[lds_pad(j + q * NB) * NF + f];
+            for (int q = 0; q < RN; ++q) vn[k][q] = src[lds_slot<L, SWZ>(j + q * NB) * NF + f];
+            C2<T> w[RN];
+            twiddles<RN, SIGN, T>(W, j * (L / (NS * RN)), w);
 #pragma unroll
-            for (int q = 1; q < RN; ++q) {
-              C2<T> w = W[(q * j * (L / (NS * RN))) % L];
-              if (SIGN > 0) w.y = -w.y;
-              vn[k][q] = cmul(vn[k][q], w);
-            }
+            for (int q = 1; q < RN; ++q) vn[k][q] = cmul(vn[k][q], w[q]);
             Butterfly<RN, SIGN, T>::run(vn[k]);
           }
         }

@@ -105,6 +105,9 @@ tc_status hip_check(tc_ctx* c, hipError_t e, const char* what);
 // launchers (return hipError_t from hipGetLastError)
 hipError_t launch_factor(tc_ctx* c, int* bad_dev);
 hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x);
+// transposed solves of nop (1, or 3 starting at OP_HP) operators on
+// consecutive fields rhs + k F -> x + k F (x may alias rhs)
+hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x);
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev_scratch,
                      cd* u_next, cd* p, int want_p);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);

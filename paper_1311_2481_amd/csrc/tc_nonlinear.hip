@@ -97,30 +97,50 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
 
 // ------------------------------------------------------------------ launch shapes
 // z kernels: NF columns per workgroup, TPF threads per column; in-place LDS.
+// Swizzled (unpadded) LDS layout in the z kernels (1: FP64 only, 2: both
+// precisions): it removes their bank conflicts and, at 1536 points, lets
+// three FP64 two-column workgroups share a CU instead of two.  Persistent
+// prefetching z workgroups (TC_Z_PREFETCH) are kept as an option for float
+// data; one tile per workgroup measured as fast and uses far fewer VGPRs.
+#ifndef TC_Z_SWIZZLE
+#define TC_Z_SWIZZLE 2
+#endif
+#ifndef TC_Z_PREFETCH
+#define TC_Z_PREFETCH 0
+#endif
 template <typename T, int L> struct ZShape {
+  static constexpr bool SWZ = (TC_Z_SWIZZLE == 2 || (TC_Z_SWIZZLE == 1 && sizeof(T) == 8)) && L % 16 == 0;
   static constexpr int TPF = L >= 512 ? (sizeof(T) == 8 ? 128 : 64) : (L >= 128 ? 32 : 8);
   // at most ~56 KB of LDS per workgroup so that two or more share a CU and
   // one's transform overlaps another's loads and stores
   static constexpr int LDS_CAP = 57344;
   static constexpr int NF0 = 256 / TPF;
-  static constexpr int NF1 = LDS_CAP / (lds_len<L>() * (int)sizeof(C2<T>));
+  static constexpr int NF1 = LDS_CAP / (lds_len<L, SWZ>() * (int)sizeof(C2<T>));
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
   static_assert(NF >= 1, "transform too long for LDS");
-  static constexpr size_t LDS = (size_t)lds_len<L>() * NF * sizeof(C2<T>);
+  static constexpr size_t LDS = (size_t)lds_len<L, SWZ>() * NF * sizeof(C2<T>);
   // persistent workgroups prefetching the next tile: pays off when the
   // prefetch registers do not lower the occupancy (float data)
-  static constexpr bool PREFETCH = sizeof(T) == 4;
+  static constexpr bool PREFETCH = TC_Z_PREFETCH && sizeof(T) == 4;
 };
 // theta kernel: TPF threads per row, RPB rows per workgroup; ping-pong
 // LDS (one barrier per exchange) or in place (two barriers, half the LDS).
+// TC_THETA_TPF8: L/8 threads per row with the inverse transform's radices
+// in reversed order, so that its last pass (and the forward transform's
+// first) is radix 8 with every thread busy.
 #ifndef TC_THETA_PINGPONG
 #define TC_THETA_PINGPONG 0
 #endif
+#ifndef TC_THETA_TPF8
+#define TC_THETA_TPF8 0
+#endif
 template <typename T, int L> struct TShape {
-  static constexpr int TPF = (L % 6 == 0) ? L / 6 : L / 8;
+  static constexpr bool TPF8 = TC_THETA_TPF8 && L % 8 == 0 && L >= 512;
+  static constexpr int TPF = TPF8 ? L / 8 : ((L % 6 == 0) ? L / 6 : L / 8);
+  static constexpr bool FIREV = TPF8;  // radix order of the inverse transform
   static constexpr int RPB = TPF >= 256 ? 1 : 256 / TPF;
   static constexpr int NBUF = TC_THETA_PINGPONG ? 2 : 1;
-  static constexpr size_t LDS = NBUF * (size_t)lds_len<L>() * RPB * sizeof(C2<T>);
+  static constexpr size_t LDS = NBUF * (size_t)lds_len<L, false>() * RPB * sizeof(C2<T>);
 };
 
 // Output weight of the forward z kernel for field fld at azimuthal index n:
@@ -159,7 +179,7 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
                                                                                const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
   constexpr int NF = Z::NF, TPF = Z::TPF;
-  using FI = Fft<T, L, TPF, +1, false>;
+  using FI = Fft<T, L, TPF, +1, false, Z::SWZ>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;
@@ -227,17 +247,26 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
 
 // ------------------------------------------------------------------ theta pass
 template <typename T, int L>
-__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_theta(Dims d, int nplanes,
+// Register budget of the theta kernel: 4 waves per SIMD (128 VGPRs) at the
+// cost of a small spill measured faster than the unconstrained 3 waves.
+#ifndef TC_THETA_WAVES
+#define TC_THETA_WAVES 4
+#endif
+__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB))
+#if TC_THETA_WAVES
+__attribute__((amdgpu_waves_per_eu(TC_THETA_WAVES)))
+#endif
+void k_theta(Dims d, int nplanes,
                                                                                  C2<T>* __restrict__ inter,
                                                                                  const C2<T>* __restrict__ W) {
   using TS = TShape<T, L>;
   constexpr int TPF = TS::TPF, RPB = TS::RPB;
-  using FI = Fft<T, L, TPF, +1, false>;
-  using FF = Fft<T, L, TPF, -1, true>;
+  using FI = Fft<T, L, TPF, +1, TS::FIREV>;
+  using FF = Fft<T, L, TPF, -1, !TS::FIREV>;
   static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
   extern __shared__ unsigned char lds_raw[];
   C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
-  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L>() * RPB : bufa;
+  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -350,11 +379,11 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
                                                                                      const C2<T>* __restrict__ W) {
   using TS = TShape<T, L>;
   constexpr int TPF = TS::TPF, RPB = TS::RPB;
-  using FI = Fft<T, L, TPF, +1, false>;
-  using FF = Fft<T, L, TPF, -1, true>;
+  using FI = Fft<T, L, TPF, +1, TS::FIREV>;
+  using FF = Fft<T, L, TPF, -1, !TS::FIREV>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
-  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L>() * RPB : bufa;
+  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -448,14 +477,14 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
   for (int k = 0; k < FF::PERN; ++k)
     if (FF::out_valid(t, k))
 #pragma unroll
-      for (int s2 = 0; s2 < FF::RN; ++s2) bufa[lds_pad(FF::out_index(t, k, s2)) * RPB + f] = o[k][s2];
+      for (int s2 = 0; s2 < FF::RN; ++s2) bufa[lds_slot<L, false>(FF::out_index(t, k, s2)) * RPB + f] = o[k][s2];
   __syncthreads();
   if (valid) {
     C2<T>* X = fld(4);
     C2<T>* Y = fld(5);
     for (int nn = t; nn < mt; nn += TPF) {
-      const C2<T> gp = bufa[lds_pad(nn) * RPB + f];
-      const C2<T> gm = cconj(bufa[lds_pad((L - nn) % L) * RPB + f]);
+      const C2<T> gp = bufa[lds_slot<L, false>(nn) * RPB + f];
+      const C2<T> gm = cconj(bufa[lds_slot<L, false>((L - nn) % L) * RPB + f]);
       X[nn] = {T(0.5) * (gp.x + gm.x), T(0.5) * (gp.y + gm.y)};
       Y[nn] = {T(0.5) * (gp.y - gm.y), T(-0.5) * (gp.x - gm.x)};
     }
@@ -469,7 +498,7 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
                                                                                const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
   constexpr int NF = Z::NF, TPF = Z::TPF;
-  using FF = Fft<T, L, TPF, -1, false>;
+  using FF = Fft<T, L, TPF, -1, false, Z::SWZ>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
   const int tiles = (d.mt + NF - 1) / NF;

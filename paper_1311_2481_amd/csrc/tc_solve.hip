@@ -176,68 +176,10 @@ __global__ __launch_bounds__(64) void k_solve(const double* __restrict__ rc, con
   }
 }
 
-// Transposed solve A^T x = rhs with A = S^-1 L U (S: the Neumann row scale of
-// P, identity for the Helmholtz operators), in the factor's row order:
-// U^T w = rhs forwards, then L^T v = w backwards, then x = S v.
-__global__ __launch_bounds__(64) void k_solve_t(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
-                                                int op, const cd* rhs, cd* x) {
-  ModeLane L;
-  if (!make_lane(d, L)) return;
-  const int M = d.n_r - 1;
-  const bool rev = (op != OP_P);
-  auto row_of = [&](int ip) { return rev ? M - ip : ip; };
-  cd w[4][2];
-  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
-  for (int ip = 0; ip <= M; ++ip) {
-    const int j = row_of(ip);
-    const double inv = facp(fac, d, op, j)[(int64_t)4 * d.ndm + L.dm];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      cd y = rhs[j * d.S + L.o[m]];
-#pragma unroll
-      for (int c = 1; c <= 4; ++c) {
-        if (ip - c >= 0) {
-          const double u = facp(fac, d, op, row_of(ip - c))[(int64_t)(4 + c) * d.ndm + L.dm];
-          y = cnfma(y, u, w[c - 1][m]);
-        }
-      }
-      y = cmuls(y, inv);
-      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
-      w[0][m] = y;
-    }
-    x[j * d.S + L.o[0]] = w[0][0];
-    x[j * d.S + L.o[1]] = w[0][1];
-  }
-  for (int q = 0; q < 4; ++q) w[q][0] = w[q][1] = cz();
-  for (int ip = M; ip >= 0; --ip) {
-    const int j = row_of(ip);
-    double scale = 1.0;
-    if (op == OP_P) scale = (j == 0) ? d.s0 : (j == M ? d.sM : 1.0);
-    if (op == OP_P && j == M && L.zero_mode) scale = 1.0;
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      cd y = x[j * d.S + L.o[m]];
-#pragma unroll
-      for (int q = 1; q <= 4; ++q) {
-        if (ip + q <= M) {
-          const double mult = facp(fac, d, op, row_of(ip + q))[(int64_t)(q - 1) * d.ndm + L.dm];
-          y = cnfma(y, mult, w[q - 1][m]);
-        }
-      }
-      for (int q = 3; q >= 1; --q) w[q][m] = w[q - 1][m];
-      w[0][m] = y;
-    }
-    x[j * d.S + L.o[0]] = cmuls(w[0][0], scale);
-    x[j * d.S + L.o[1]] = cmuls(w[0][1], scale);
-  }
-}
-
 hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x) {
+  if (transposed) return launch_solve_t(c, op, 1, rhs, x);
   const int blocks = (c->d.ndm + 63) / 64;
-  if (transposed)
-    hipLaunchKernelGGL(k_solve_t, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, op, rhs, x);
-  else
-    hipLaunchKernelGGL(k_solve, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, op, rhs, x);
+  hipLaunchKernelGGL(k_solve, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, op, rhs, x);
   return hipGetLastError();
 }
 
@@ -515,6 +457,117 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
       if (want_p) p[on] = cz();
     }
   }
+}
+
+// Transposed solve A^T x = rhs with A = S^-1 L U (S: the Neumann row scale of
+// P, identity for the Helmholtz operators), in the factor's row order:
+// U^T w = rhs forwards, then L^T v = w backwards, then x = S v.
+// NOP operators at once (ops op0..op0+NOP-1, fields
+// rhs + k F -> x + k F), one mode per lane (the Lane1 layout of the
+// predictor-corrector below).  Rows are taken CH at a time: the loads of a
+// chunk are all issued before its recurrence runs, so a sweep waits for
+// memory once per chunk rather than once per row (small problems, where
+// there are too few waves to hide the latency, are bound by exactly that).
+template <int NOP, int CH>
+__global__ __launch_bounds__(64) void k_solve_tn(const double* __restrict__ fac, Dims d, int op0, const cd* rhs, cd* x) {
+  Lane1 L;
+  if (!make_lane1(d, L)) return;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  // ops 1-3 (Helmholtz) are factored in descending row order, P ascending
+  const bool rev = (op0 != OP_P);
+  auto row_of = [&](int ip) { return rev ? M - ip : ip; };
+  auto fw = [&](int op, int ip, int c) { return facp(fac, d, op, row_of(ip))[(int64_t)c * d.ndm + L.dm]; };
+  cd w[NOP][4];
+#pragma unroll
+  for (int k = 0; k < NOP; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[k][q] = cz();
+  // U^T w = rhs, in processing order
+  for (int ip0 = 0; ip0 <= M; ip0 += CH) {
+    cd r[CH][NOP];
+    double inv[CH][NOP], uc[CH][NOP][4];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int ip = ip0 + t;
+      if (ip > M) continue;
+      const int j = row_of(ip);
+#pragma unroll
+      for (int k = 0; k < NOP; ++k) {
+        r[t][k] = rhs[k * F + j * S + L.o];
+        inv[t][k] = fw(op0 + k, ip, 4);
+#pragma unroll
+        for (int c = 1; c <= 4; ++c) uc[t][k][c - 1] = (ip - c >= 0) ? fw(op0 + k, ip - c, 4 + c) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int ip = ip0 + t;
+      if (ip > M) continue;
+      const int j = row_of(ip);
+#pragma unroll
+      for (int k = 0; k < NOP; ++k) {
+        cd y = r[t][k];
+#pragma unroll
+        for (int c = 1; c <= 4; ++c) y = cnfma(y, uc[t][k][c - 1], w[k][c - 1]);
+        y = cmuls(y, inv[t][k]);
+#pragma unroll
+        for (int q = 3; q >= 1; --q) w[k][q] = w[k][q - 1];
+        w[k][0] = y;
+        x[k * F + j * S + L.o] = y;
+      }
+    }
+  }
+  // L^T v = w backwards, then x = S v (S: Neumann row scale of P)
+#pragma unroll
+  for (int k = 0; k < NOP; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[k][q] = cz();
+  for (int ip0 = M; ip0 >= 0; ip0 -= CH) {
+    cd r[CH][NOP];
+    double mc[CH][NOP][4];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int ip = ip0 - t;
+      if (ip < 0) continue;
+      const int j = row_of(ip);
+#pragma unroll
+      for (int k = 0; k < NOP; ++k) {
+        r[t][k] = x[k * F + j * S + L.o];
+#pragma unroll
+        for (int q = 1; q <= 4; ++q) mc[t][k][q - 1] = (ip + q <= M) ? fw(op0 + k, ip + q, q - 1) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int ip = ip0 - t;
+      if (ip < 0) continue;
+      const int j = row_of(ip);
+      double scale = 1.0;
+      if (op0 == OP_P && !(j == M && L.zero_mode)) scale = (j == 0) ? d.s0 : (j == M ? d.sM : 1.0);
+#pragma unroll
+      for (int k = 0; k < NOP; ++k) {
+        cd y = r[t][k];
+#pragma unroll
+        for (int q = 1; q <= 4; ++q) y = cnfma(y, mc[t][k][q - 1], w[k][q - 1]);
+#pragma unroll
+        for (int q = 3; q >= 1; --q) w[k][q] = w[k][q - 1];
+        w[k][0] = y;
+        x[k * F + j * S + L.o] = cmuls(y, scale);
+      }
+    }
+  }
+}
+
+hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
+  const int blocks = (c->d.ndm + 31) / 32;
+  if (nop == 1)
+    hipLaunchKernelGGL((k_solve_tn<1, 8>), dim3(blocks), dim3(64), 0, c->stream, c->fac, c->d, op0, rhs, x);
+  else if (nop == 3 && op0 == OP_HP)
+    hipLaunchKernelGGL((k_solve_tn<3, 4>), dim3(blocks), dim3(64), 0, c->stream, c->fac, c->d, op0, rhs, x);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
