@@ -140,7 +140,7 @@ void twiddles(int L, std::vector<C2<T>>& out) {
 void free_ctx(tc_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rc_dev, c->fac, c->tw_t, c->tw_z, c->twf_t, c->twf_z, c->u, c->u_prev, c->N_prev,
-                  c->N_cur, c->p, c->omega, c->aux, c->inter};
+                  c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax};
   for (void* p : ptrs) dev_free(p);
   for (auto& t : c->timers)
     for (auto e : t.ev) (void)hipEventDestroy(e);
@@ -420,6 +420,7 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   c->N_cur = dev_alloc<cd>(c, 3 * FB, st);
   c->p = dev_alloc<cd>(c, FB, st);
   c->omega = dev_alloc<cd>(c, 3 * FB, st);
+  c->zmax = dev_alloc<unsigned int>(c, (size_t)ZMAX_WORDS * d.n_r * sizeof(unsigned int), st);
   // plane batch of the nonlinear term: all planes when they fit a budget
   {
     const size_t per = inter_bytes_per_plane(c);

@@ -47,11 +47,17 @@ struct KernelTimer {
 // taken from (or written to) separate spectral arrays, nf_plane fields per
 // radial plane in the transform-layout buffer.  For the forward kernel the
 // output is multiplied by scale (and by Hermitian weights when weights = 1).
+// zmax (inverse kernel, optional): per batch plane, ZMAX_WORDS words; input
+// field k adds its largest |component| (as float bits, a maximum) to word
+// zmax_slot[k] of its plane (-1: not recorded).  Cleared by the launcher.
+constexpr int ZMAX_WORDS = 4;
 struct ZIo {
   const C2<double>* src[9];
   C2<double>* dst[9];
   int nfields, nf_plane, weights;
   double scale;
+  unsigned int* zmax;
+  int zmax_slot[9];
 };
 
 struct Dims {
@@ -87,6 +93,7 @@ struct tc_ctx {
   tc::cd* aux = nullptr;     // adjoint work (allocated on first use)
   size_t aux_bytes = 0;
   void* inter = nullptr;     // nonlinear intermediate, batch planes
+  unsigned int* zmax = nullptr;  // per-plane field magnitudes (ZMAX_WORDS n_r words)
   int batch = 0;
   size_t bytes = 0;
   int64_t steps = 0;

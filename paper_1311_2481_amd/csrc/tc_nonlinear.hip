@@ -89,11 +89,20 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dim
   }
 }
 
+__global__ void k_clear_words(unsigned int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
   const int64_t blocks = (c->d.S + 255) / 256;
   hipLaunchKernelGGL(k_curl, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, omega);
   return hipGetLastError();
 }
+
+// Scaled packing of u_z and omega_z in the float azimuthal transforms.
+#ifndef TC_F32_ZSCALE
+#define TC_F32_ZSCALE 1
+#endif
 
 // ------------------------------------------------------------------ launch shapes
 // z kernels: NF columns per workgroup, TPF threads per column; in-place LDS.
@@ -153,22 +162,35 @@ __device__ __forceinline__ double z_out_weight(int weights, int fld, int n) {
   return n == 0 ? 1.0 : 2.0;
 }
 
-// Persistent z kernels: gridDim.x workgroups loop over all column tiles,
-// loading the next tile into registers while the current one is being
-// transformed (the LDS then never waits on memory).  Workgroups on one XCD
-// (8 of them, assigned round robin) take tiles of one contiguous range, so
-// neighbouring column tiles, which share cache lines, go through the same L2.
+// Tile walk of the persistent z kernels: workgroup b belongs to XCD group b % G; the
+// groups own contiguous, disjoint tile ranges that together cover every
+// tile, and the workgroups of a group stride through its range starting at
+// their slot b / G.  G = 8 (workgroups are dispatched round
+// robin over the 8 XCDs, so neighbouring column tiles, which share cache
+// lines, go through the same L2), or the number of workgroups if that is
+// smaller, so that every group has at least one workgroup: every tile is
+// then transformed exactly once for any grid size.
+// With TC_Z_PREFETCH the next tile is loaded into registers while the
+// current one is transformed (persistent grids).
+// One tile per workgroup (the default): the grid is 8 ceil(ntiles / 8)
+// workgroups and workgroup b takes tile (b % 8) ceil(ntiles / 8) + b / 8, a
+// bijection that gives each XCD a contiguous range; tiles past the end
+// belong to padding workgroups, which return -1.
+__device__ __forceinline__ int single_tile(int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  const int id = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  return id < ntiles ? id : -1;
+}
+
 struct TileWalk {
-  int xcd, per_xcd, first, last;
+  int per_group, first, last;
   __device__ TileWalk(int ntiles) {
     const int g = gridDim.x;
-    xcd = blockIdx.x % 8;
-    const int nx = (g + 7 - xcd) / 8;           // workgroups on this XCD
-    const int slot = blockIdx.x / 8;
-    const int lo = (int)((int64_t)ntiles * xcd / 8), hi = (int)((int64_t)ntiles * (xcd + 1) / 8);
-    per_xcd = nx;
-    first = lo + slot;
-    last = hi;
+    const int G = g < 8 ? g : 8;
+    const int grp = blockIdx.x % G;
+    per_group = (g - grp + G - 1) / G;  // workgroups in this group
+    first = (int)((int64_t)ntiles * grp / G) + (int)(blockIdx.x / G);
+    last = (int)((int64_t)ntiles * (grp + 1) / G);
   }
 };
 
@@ -186,7 +208,6 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
   const int ntiles = tiles * io.nfields * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int h = d.half;
-  TileWalk tw(ntiles);
   auto load = [&](int id, cd (&raw)[FI::PER0][FI::R0]) {
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
@@ -223,12 +244,31 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
           for (int s2 = 0; s2 < FI::RN; ++s2) dst[(int64_t)FI::out_index(t, k, s2) * d.mt] = vo[k][s2];
     }
   };
+  // per-plane magnitude of two of the input fields (see ZIo::zmax): a wave
+  // maximum, then one atomic per wave
+  auto record = [&](int id, const cd (&raw)[FI::PER0][FI::R0]) {
+    if (io.zmax == nullptr) return;
+    const int rest = id / tiles;
+    const int fld = rest % io.nfields, pl = rest / io.nfields;
+    const int which = io.zmax_slot[fld];
+    if (which < 0) return;
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+      for (int q = 0; q < FI::R0; ++q) m = fmaxf(m, (float)fmax(fabs(raw[k][q].x), fabs(raw[k][q].y)));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    // non-negative floats order as their bit patterns
+    if ((threadIdx.x & 63) == 0) atomicMax(io.zmax + ZMAX_WORDS * pl + which, __float_as_uint(m));
+  };
   if constexpr (Z::PREFETCH) {
     cd cur[FI::PER0][FI::R0], nxt[FI::PER0][FI::R0];
+    TileWalk tw(ntiles);
     if (tw.first < tw.last) load(tw.first, cur);
-    for (int id = tw.first; id < tw.last; id += tw.per_xcd) {
-      const int idn = id + tw.per_xcd;
+    for (int id = tw.first; id < tw.last; id += tw.per_group) {
+      const int idn = id + tw.per_group;
       if (idn < tw.last) load(idn, nxt);
+      record(id, cur);
       transform_store(id, cur);
 #pragma unroll
       for (int k = 0; k < FI::PER0; ++k)
@@ -236,29 +276,30 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
         for (int q = 0; q < FI::R0; ++q) cur[k][q] = nxt[k][q];
     }
   } else {
-    // one tile per workgroup
+    const int id = single_tile(ntiles);
+    if (id < 0) return;  // padding workgroup (uniform over the workgroup)
     cd cur[FI::PER0][FI::R0];
-    if (tw.first < tw.last) {
-      load(tw.first, cur);
-      transform_store(tw.first, cur);
-    }
+    load(id, cur);
+    record(id, cur);
+    transform_store(id, cur);
   }
 }
 
 // ------------------------------------------------------------------ theta pass
 template <typename T, int L>
-// Register budget of the theta kernel: 4 waves per SIMD (128 VGPRs) at the
-// cost of a small spill measured faster than the unconstrained 3 waves.
+// Register budget of the theta kernel at lengths >= 1024: in double 4 waves
+// per SIMD (128 VGPRs), at the cost of a small spill measured faster than
+// the unconstrained 3 waves; in float 6 waves.  Shorter rows keep the
+// compiler's choice.
 #ifndef TC_THETA_WAVES
 #define TC_THETA_WAVES 4
 #endif
 __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB))
 #if TC_THETA_WAVES
-__attribute__((amdgpu_waves_per_eu(TC_THETA_WAVES)))
+__attribute__((amdgpu_waves_per_eu(L >= 1024 ? (sizeof(T) == 8 ? TC_THETA_WAVES : 6) : 1)))
 #endif
-void k_theta(Dims d, int nplanes,
-                                                                                 C2<T>* __restrict__ inter,
-                                                                                 const C2<T>* __restrict__ W) {
+void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter, const C2<T>* __restrict__ W,
+             const unsigned int* __restrict__ zmax) {
   using TS = TShape<T, L>;
   constexpr int TPF = TS::TPF, RPB = TS::RPB;
   using FI = Fft<T, L, TPF, +1, TS::FIREV>;
@@ -279,7 +320,8 @@ void k_theta(Dims d, int nplanes,
 
   // spectrum of h_u (which 0), h_omega (1) or g = u_z + i omega_z (2) at
   // azimuthal index e (n = e or e - L)
-  auto spec = [&](int which, int e) -> C2<T> {
+  // which = 2: g = u_z + i sw omega_z (sw: see below)
+  auto spec = [&](int which, int e, T sw) -> C2<T> {
     const C2<T>* A = base + (int64_t)(which == 0 ? 0 : (which == 1 ? 3 : 2)) * fstride;
     const C2<T>* B = base + (int64_t)(which == 0 ? 1 : (which == 1 ? 4 : 5)) * fstride;
     const int nn = (e <= L / 2) ? e : e - L;
@@ -295,29 +337,53 @@ void k_theta(Dims d, int nplanes,
     } else {
       if (nn > 0 && nn < mt) {
         const C2<T> x = A[nn], y = B[nn];
-        v = {x.x - y.y, x.y + y.x};
+        v = {x.x - sw * y.y, x.y + sw * y.x};
       } else if (nn < 0 && -nn < mt) {
         const C2<T> x = cconj(A[-nn]), y = cconj(B[-nn]);
-        v = {x.x - y.y, x.y + y.x};
+        v = {x.x - sw * y.y, x.y + sw * y.x};
       } else if (nn == 0) {
-        v = {A[0].x, B[0].x};
+        v = {A[0].x, sw * B[0].x};
       }
     }
     return v;
   };
   typename FI::In v0;
   typename FI::Out hu, hw, g;
-  auto inverse = [&](int which, typename FI::Out& out) {
+  auto inverse = [&](int which, typename FI::Out& out, T sw) {
 #pragma unroll
     for (int k = 0; k < FI::PER0; ++k)
 #pragma unroll
       for (int q = 0; q < FI::R0; ++q)
-        v0[k][q] = FI::in_valid(t, k) ? spec(which, FI::in_index(t, k, q)) : C2<T>{T(0), T(0)};
+        v0[k][q] = FI::in_valid(t, k) ? spec(which, FI::in_index(t, k, q), sw) : C2<T>{T(0), T(0)};
     FI::template run<RPB>(v0, out, bufa, bufb, W, t, f);
   };
-  inverse(0, hu);
-  inverse(1, hw);
-  inverse(2, g);
+  // g carries u_z and omega_z in one complex transform, whose rounding error
+  // delta follows its larger part.  In the products, u_z's error is weighted
+  // by |h_omega| and omega_z's by |h_u|, so with g = u_z + i sw omega_z the
+  // error of N is about delta (|h_omega| + |h_u| / sw) with delta ~ |u_z| +
+  // sw |omega_z|; it is smallest at sw^2 = |u_z| |h_u| / (|omega_z| |h_omega|).
+  // In float, sw is that value rounded to a power of two, from the plane's
+  // largest coefficients (recorded by the axial inverse kernel), and omega_z
+  // is unscaled after the transform (both exact).  In double the unscaled
+  // packing costs at most ~1e-13 relative and is kept.
+  int ez = 0;
+  if constexpr (sizeof(T) == 4) {
+    if (zmax != nullptr) {
+      float m[ZMAX_WORDS];
+      bool ok = true;
+#pragma unroll
+      for (int w = 0; w < ZMAX_WORDS; ++w) {
+        m[w] = __uint_as_float(zmax[ZMAX_WORDS * pl + w]);
+        ok = ok && m[w] > 0.f && m[w] < 3e38f;
+      }
+      if (ok) ez = (ilogbf(m[0]) + ilogbf(m[2]) - ilogbf(m[1]) - ilogbf(m[3])) / 2;
+      ez = ez < -40 ? -40 : (ez > 40 ? 40 : ez);
+    }
+  }
+  const T sw = ldexp(T(1), ez), isw = ldexp(T(1), -ez);
+  inverse(0, hu, T(1));
+  inverse(1, hw, T(1));
+  inverse(2, g, sw);
   // pointwise products (the slots hold the same points for all three)
   typename FF::In hn, nz;
 #pragma unroll
@@ -325,7 +391,7 @@ void k_theta(Dims d, int nplanes,
 #pragma unroll
     for (int q = 0; q < FI::RN; ++q) {
       const C2<T> a = hu[k][q], w = hw[k][q];
-      const T uzv = g[k][q].x, wzv = g[k][q].y;
+      const T uzv = g[k][q].x, wzv = g[k][q].y * isw;
       hn[k][q] = {uzv * w.y - wzv * a.y, wzv * a.x - uzv * w.x};
       nz[k][q] = {w.x * a.y - w.y * a.x, T(0)};
     }
@@ -505,7 +571,6 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   const int ntiles = tiles * io.nfields * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int h = d.half;
-  TileWalk tw(ntiles);
   auto load = [&](int id, typename FF::In& v) {
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
@@ -545,9 +610,10 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   };
   if constexpr (Z::PREFETCH) {
     typename FF::In cur, nxt;
+    TileWalk tw(ntiles);
     if (tw.first < tw.last) load(tw.first, cur);
-    for (int id = tw.first; id < tw.last; id += tw.per_xcd) {
-      const int idn = id + tw.per_xcd;
+    for (int id = tw.first; id < tw.last; id += tw.per_group) {
+      const int idn = id + tw.per_group;
       if (idn < tw.last) load(idn, nxt);
       transform_store(id, cur);
 #pragma unroll
@@ -556,11 +622,11 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
         for (int q = 0; q < FF::R0; ++q) cur[k][q] = nxt[k][q];
     }
   } else {
+    const int id = single_tile(ntiles);
+    if (id < 0) return;  // padding workgroup (uniform over the workgroup)
     typename FF::In cur;
-    if (tw.first < tw.last) {
-      load(tw.first, cur);
-      transform_store(tw.first, cur);
-    }
+    load(id, cur);
+    transform_store(id, cur);
   }
 }
 
@@ -582,8 +648,8 @@ size_t inter_bytes_per_plane(const tc_ctx* c) {
 // Workgroups of a z kernel: with prefetching a few per CU (256 CUs), each
 // walking many tiles; without, one per tile.
 static unsigned z_blocks(int64_t ntiles, bool prefetch) {
-  const int64_t cap = prefetch ? 256 * 8 : ntiles;
-  return (unsigned)(ntiles < cap ? ntiles : cap);
+  if (prefetch) return (unsigned)(ntiles < 256 * 8 ? ntiles : 256 * 8);
+  return (unsigned)(8 * ((ntiles + 7) / 8));  // see single_tile
 }
 
 template <typename T, int L>
@@ -616,7 +682,7 @@ static hipError_t run_theta(tc_ctx* c, int np, const C2<T>* W) {
   const int64_t rows = (int64_t)np * c->d.pz;
   const unsigned blocks = (unsigned)((rows + TS::RPB - 1) / TS::RPB);
   hipLaunchKernelGGL((k_theta<T, L>), dim3(blocks), dim3(TS::TPF * TS::RPB), lds, c->stream, c->d, np,
-                     reinterpret_cast<C2<T>*>(c->inter), W);
+                     reinterpret_cast<C2<T>*>(c->inter), W, TC_F32_ZSCALE ? (const unsigned int*)c->zmax : nullptr);
   return hipGetLastError();
 }
 
@@ -645,7 +711,18 @@ hipError_t launch_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om)
   }
   io.nfields = 6;
   io.nf_plane = 6;
-  return launch_zinv_io(c, plane0, np, io, c->inter, c->g.precision == TC_FP32_BULK);
+  const bool f32 = c->g.precision == TC_FP32_BULK;
+  if (f32 && TC_F32_ZSCALE) {
+    // per-plane magnitudes of u_z, omega_z, u+- and omega+-, for the scaled
+    // packing of the azimuthal float transforms
+    io.zmax = c->zmax;
+    const int slot[6] = {2, 2, 0, 3, 3, 1};
+    for (int k = 0; k < 9; ++k) io.zmax_slot[k] = k < 6 ? slot[k] : -1;
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, c->stream, c->zmax, ZMAX_WORDS * np);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_zinv_io(c, plane0, np, io, c->inter, f32);
 }
 
 hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, bool f32) {

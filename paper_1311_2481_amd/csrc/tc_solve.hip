@@ -173,6 +173,8 @@ __global__ __launch_bounds__(64) void k_solve(const double* __restrict__ rc, con
     }
     x[j * d.S + L.o[0]] = w[0][0];
     x[j * d.S + L.o[1]] = w[0][1];
+    // the empty axial slot is written as zero (by the |l| = 0 lanes)
+    if (L.labs == 0) x[j * d.S + (int64_t)d.nyq * d.mt + L.n] = cz();
   }
 }
 
@@ -518,7 +520,10 @@ __global__ __launch_bounds__(64) void k_solve_tn(const double* __restrict__ fac,
       }
     }
   }
-  // L^T v = w backwards, then x = S v (S: Neumann row scale of P)
+  // L^T v = w backwards, then x = S v (S: Neumann row scale of P); the
+  // |l| = 0, +l lanes also write the empty axial slot as zero
+  const bool nyq_lane = (L.dm < d.mt) && (threadIdx.x < 32);
+  const int64_t onyq = (int64_t)d.nyq * d.mt + L.dm;
 #pragma unroll
   for (int k = 0; k < NOP; ++k)
 #pragma unroll
@@ -554,6 +559,7 @@ __global__ __launch_bounds__(64) void k_solve_tn(const double* __restrict__ fac,
         for (int q = 3; q >= 1; --q) w[k][q] = w[k][q - 1];
         w[k][0] = y;
         x[k * F + j * S + L.o] = cmuls(y, scale);
+        if (nyq_lane) x[k * F + j * S + onyq] = cz();
       }
     }
   }

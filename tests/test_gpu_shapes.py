@@ -1,0 +1,94 @@
+"""Every supported transform length, in both directions, with ragged mode
+counts: the nonlinear term (FP64 and FP32-bulk) and one full step against the
+oracle on small radial grids.
+
+Each case sets the dealiased grid (P_theta, P_z) explicitly and stores the
+largest mode counts that the 3/2 rule allows for it (P_theta >= 3 m_theta - 2,
+P_z >= 3 m_z / 2 - 2), so most cases have odd m_theta and distinct-mode
+counts that are not multiples of the kernels' tiles: the last tile of every
+kernel is partial.  Inputs are unstructured seeded coefficients with a
+real-field-consistent n = 0 plane.
+"""
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+import oracle
+import tc_inputs
+from oracle import nonlinear as nl
+from oracle import scheme
+from gpu_common import rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+# theta length i is paired with z length i + 5 (cyclically): every length is
+# used once along theta and once along z
+CASES = [(LENGTHS[i], LENGTHS[(i + 5) % len(LENGTHS)]) for i in range(len(LENGTHS))]
+# full steps on grids whose distinct-mode counts keep the oracle's per-mode
+# factorisations quick, still reaching the shortest and longest transforms
+STEP_CASES = [(32, 48), (96, 24), (256, 64), (24, 384), (2048, 16), (64, 1536)]
+
+
+def _pair(p_theta, p_z, precision, n_r=11):
+    from paper_1311_2481_amd import Solver
+    m_theta = (p_theta + 2) // 3
+    m_z = 2 * ((p_z + 2) // 3)
+    args = (n_r, m_theta, m_z, 0.6, 80.0, -20.0, 1e-3)
+    S = Solver(*args, k_theta=1.5, k_z=0.8, precision=precision, p_theta=p_theta, p_z=p_z)
+    P = oracle.Problem(*args, k_theta=1.5, k_z=0.8, p_theta=p_theta, p_z=p_z)
+    return S, P
+
+
+def _nonlinear_float32(P, u):
+    """Yardstick for the FP32-bulk form: the oracle's steps with the curl in
+    double and the transforms and products in single precision (scipy.fft
+    keeps float32), i.e. the rounding any float32 evaluation of this term
+    incurs."""
+    ur, ut, uz = nl.cylindrical(u)
+    wr, wt, wz = nl.vorticity(P, u)
+
+    def phys(f):
+        return sfft.irfft2(nl._pad(P, f).astype(np.complex64), s=(P.p_z, P.p_theta), axes=(-2, -1), norm="forward")
+    U, W = phys(np.stack([ur, ut, uz])), phys(np.stack([wr, wt, wz]))
+    prod = np.stack([W[1] * U[2] - W[2] * U[1], W[2] * U[0] - W[0] * U[2], W[0] * U[1] - W[1] * U[0]])
+    spec = nl._truncate(P, sfft.rfft2(prod, axes=(-2, -1), norm="forward"))
+    return nl.plus_minus(*spec)
+
+
+@pytest.mark.parametrize("p_theta,p_z", CASES)
+def test_nonlinear_all_lengths(p_theta, p_z):
+    for precision in ("fp64", "fp32_bulk"):
+        S, P = _pair(p_theta, p_z, precision)
+        u = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), p_theta + 7 * p_z)
+        ref = oracle.nonlinear_rot(P, u)
+        err = rel_l2(to_host(S.nonlinear(to_dev(u))), ref)
+        if precision == "fp64":
+            tol = 1e-12
+        else:
+            # within a small factor of what float32 transforms of the same
+            # (unstructured, white) spectra give; that error grows with the
+            # transform lengths, from ~1e-7 to ~1e-5 over these grids
+            tol = 8.0 * rel_l2(_nonlinear_float32(P, u), ref)
+        print(f"P_theta={p_theta} P_z={p_z} m_theta={P.m_theta} m_z={P.m_z} {precision}: "
+              f"nonlinear rel_l2 {err:.2e} (bound {tol:.1e})")
+        assert err < tol
+        S.close()
+
+
+@pytest.mark.parametrize("p_theta,p_z", STEP_CASES)
+def test_step_all_lengths(p_theta, p_z):
+    S, P = _pair(p_theta, p_z, "fp64")
+    u = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), 3 * p_theta + p_z)
+    up = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), 5 * p_theta + p_z)
+    Np = oracle.nonlinear_rot(P, up)
+    S.set_state(to_dev(u), to_dev(up), to_dev(Np))
+    S.step(1)
+    got, p = S.get_state()
+    ref_u, ref_p, _ = scheme.step(P, u, up, Np)
+    eu, ep = rel_l2(to_host(got), ref_u), rel_l2(to_host(p), ref_p)
+    print(f"P_theta={p_theta} P_z={p_z}: one step u rel_l2 {eu:.2e}, p rel_l2 {ep:.2e}")
+    # unstructured input makes the correction phi as large as u itself, so
+    # the conditioning of the Neumann Poisson solve shows directly in u
+    assert eu < 1e-10 and ep < 1e-9
+    S.close()
