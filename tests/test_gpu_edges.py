@@ -1,0 +1,114 @@
+"""Degenerate and extreme grids against the oracle, and the out-of-memory path.
+
+* smallest grid: n_r = 9 (one full 9-point stencil), a single azimuthal mode
+  (axisymmetric) and a single axial mode pair (m_z = 2: l = 0 and the empty
+  slot), on the shortest supported transforms (16 x 16);
+* tallest radial grid the library accepts (n_r = 4096) with few modes;
+* the zero state, whose nonlinear term and step must be exactly zero;
+* a grid too large for the device: tc_init must fail with TC_ENOMEM and
+  leave the device usable.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tc_inputs
+from oracle import scheme
+from gpu_common import rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(n_r, m_theta, m_z, p_theta=16, p_z=16, Re_i=50.0, Re_o=10.0, dt=1e-3):
+    from paper_1311_2481_amd import Solver
+    args = (n_r, m_theta, m_z, 0.5, Re_i, Re_o, dt)
+    S = Solver(*args, p_theta=p_theta, p_z=p_z)
+    P = oracle.Problem(*args, p_theta=p_theta, p_z=p_z)
+    return S, P
+
+
+def _jittered(P, seed):
+    """The same problem on nodes moved by independent one-ulp perturbations
+    (walls fixed), with its FD weights rebuilt: the two sides round the node
+    formula independently, and next to clustered walls a one-ulp move of a
+    node is ~1e-9 of the local spacing, so this distance is the rounding
+    floor of a result."""
+    from oracle.radial import fd_matrices
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q = oracle.Problem(P.n_r, P.m_theta, P.m_z, P.eta, P.Re_i, P.Re_o, P.dt, p_theta=P.p_theta, p_z=P.p_z)
+    r = P.r.copy()
+    r[1:-1] *= 1.0 + 1.1e-16 * rng.choice([-1.0, 1.0], size=P.n_r - 2)
+    Q.r = r
+    Q.D1, Q.D2 = fd_matrices(r)
+    return Q
+
+
+@pytest.mark.parametrize("n_r,m_theta,m_z", [(9, 1, 2), (9, 2, 4), (4096, 3, 4)])
+def test_extreme_grids_step(n_r, m_theta, m_z):
+    S, P = _pair(n_r, m_theta, m_z)
+    shape = (3, n_r, m_z, m_theta)
+    u = tc_inputs.random_state(shape, n_r + m_theta)
+    up = tc_inputs.random_state(shape, n_r + m_theta + 1)
+    N = to_host(S.nonlinear(to_dev(u)))
+    ref_N = oracle.nonlinear_rot(P, u)
+    eN = rel_l2(N, ref_N)
+    Np = oracle.nonlinear_rot(P, up)
+    S.set_state(to_dev(u), to_dev(up), to_dev(Np))
+    S.step(1)
+    got, p = S.get_state()
+    ref_u, ref_p, _ = scheme.step(P, u, up, Np)
+    eu, ep = rel_l2(to_host(got), ref_u), rel_l2(to_host(p), ref_p)
+    # rounding floor: unstructured radial data meets D1 weights of order
+    # 1/h_min near the clustered walls (h_min ~ 3e-7 at n_r = 4096), and the
+    # correction phi of unstructured input is as large as u itself
+    Q = _jittered(P, 11)
+    fN = rel_l2(oracle.nonlinear_rot(Q, u), ref_N)
+    qu, qp, _ = scheme.step(Q, u, up, Np)
+    fu, fp = rel_l2(qu, ref_u), rel_l2(qp, ref_p)
+    print(f"n_r={n_r} m_theta={m_theta} m_z={m_z}: nonlinear {eN:.2e} (floor {fN:.1e}), "
+          f"step u {eu:.2e} (floor {fu:.1e}), p {ep:.2e} (floor {fp:.1e})")
+    assert eN < max(1e-12, 10 * fN)
+    assert eu < max(1e-10, 10 * fu) and ep < max(1e-9, 10 * fp)
+    # the empty axial slot stays zero
+    assert np.all(to_host(got)[:, :, m_z // 2] == 0)
+    S.close()
+
+
+def test_zero_state_is_a_fixed_point():
+    # with both cylinders at rest the zero flow is a solution of the discrete
+    # step: the nonlinear term and every right-hand side vanish exactly
+    S, P = _pair(16, 4, 8, Re_i=0.0, Re_o=0.0)
+    z = S.zeros(3)
+    assert to_host(S.nonlinear(z)).any() == False  # noqa: E712
+    S.set_state(z)
+    S.step(3)
+    u, p = S.get_state()
+    assert not to_host(u).any() and not to_host(p).any()
+    S.close()
+
+
+def test_step_zero_and_history_defaults():
+    # tc_step(0) changes nothing; u_prev = NULL means u_prev = u, N_prev =
+    # NULL means N(u_prev)
+    S, P = _pair(12, 3, 6)
+    u = tc_inputs.random_state((3, 12, 6, 3), 77)
+    S.set_state(to_dev(u))
+    S.step(0)
+    assert np.array_equal(to_host(S.get_state(with_pressure=False)), u)
+    up, Np = S.get_history()
+    assert np.array_equal(to_host(up), u)
+    assert rel_l2(to_host(Np), oracle.nonlinear_rot(P, u)) < 1e-12
+    S.close()
+
+
+def test_out_of_memory_is_reported_and_recoverable():
+    from paper_1311_2481_amd import Solver, TcError
+    # one field of this grid is 61 GB; the state alone needs 16 of them
+    with pytest.raises(TcError) as err:
+        Solver(4096, 683, 1366, 0.5, 100.0, 0.0, 1e-4, p_theta=2048, p_z=2048)
+    assert "ENOMEM" in str(err.value)
+    # the device is still usable afterwards
+    S, P = _pair(9, 1, 2)
+    u = tc_inputs.random_state((3, 9, 2, 1), 3)
+    assert rel_l2(to_host(S.nonlinear(to_dev(u))), oracle.nonlinear_rot(P, u)) < 1e-12
+    S.close()
