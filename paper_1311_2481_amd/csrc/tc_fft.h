@@ -201,6 +201,32 @@ __device__ __forceinline__ void twiddles(const C2<T>* __restrict__ W, int base, 
   }
 }
 
+// v[q] *= w^q, q = 1..R-1.  In double with TC_TW_CHAIN the powers are formed
+// one after another (w^q = w^(q-1) w, a few ulp), so that only two twiddles
+// are live: register pressure decides the occupancy of the long transforms.
+#ifndef TC_TW_CHAIN
+#define TC_TW_CHAIN 1
+#endif
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void apply_twiddles(const C2<T>* __restrict__ W, int base, C2<T>* v) {
+  if constexpr (TC_TW_CHAIN && sizeof(T) == 8 && R > 2) {
+    C2<T> w1 = W[base];
+    if (SIGN > 0) w1.y = -w1.y;
+    C2<T> wq = w1;
+    v[1] = cmul(v[1], w1);
+#pragma unroll
+    for (int q = 2; q < R; ++q) {
+      wq = cmul(wq, w1);
+      v[q] = cmul(v[q], wq);
+    }
+  } else {
+    C2<T> w[R];
+    twiddles<R, SIGN, T>(W, base, w);
+#pragma unroll
+    for (int q = 1; q < R; ++q) v[q] = cmul(v[q], w[q]);
+  }
+}
+
 template <typename T, int L, int TPF, int SIGN, bool REV, bool SWZ = false>
 struct Fft {
   static constexpr RadixList RL = REV ? reversed(make_radices(L)) : make_radices(L);
@@ -236,10 +262,7 @@ struct Fft {
       const int j = t + k * TPF;
       if (NB % TPF == 0 || j < NB) {
         const int kk = j % NS;
-        C2<T> w[R];
-        twiddles<R, SIGN, T>(W, kk * (L / (NS * R)), w);  // q kk L/(NS R) < L
-#pragma unroll
-        for (int q = 1; q < R; ++q) v[k][q] = cmul(v[k][q], w[q]);
+        apply_twiddles<R, SIGN, T>(W, kk * (L / (NS * R)), v[k]);  // q kk L/(NS R) < L
         Butterfly<R, SIGN, T>::run(v[k]);
         const int base = (j / NS) * NS * R + kk;
 #pragma unroll
@@ -303,10 +326,7 @@ struct Fft {
           if (NB % TPF == 0 || j < NB) {
 #pragma unroll
             for (int q = 0; q < RN; ++q) vn[k][q] = src[lds_slot<L, SWZ>(j + q * NB) * NF + f];
-            C2<T> w[RN];
-            twiddles<RN, SIGN, T>(W, j * (L / (NS * RN)), w);
-#pragma unroll
-            for (int q = 1; q < RN; ++q) vn[k][q] = cmul(vn[k][q], w[q]);
+            apply_twiddles<RN, SIGN, T>(W, j * (L / (NS * RN)), vn[k]);
             Butterfly<RN, SIGN, T>::run(vn[k]);
           }
         }
