@@ -161,6 +161,45 @@ def adjoint_ratio(repeats=3):
                          f"checkpoint every {every}; median of {repeats}")}
 
 
+def adjoint_step_at_scale(cfg, n_r=256, reps=3):
+    """One reverse step (tc_step_adjoint) on the production planes with half
+    the radial nodes (the full production adjoint does not fit in one GPU's
+    memory).  Algorithmic bytes: read u^i (3 fields) and the cotangent
+    (9), write the cotangent of the inputs (9), and one pass over the
+    factors of the five transposed solves (P twice, H+-, H_z)."""
+    import torch
+    import tc_inputs
+    from paper_1311_2481_amd import Solver
+    S = Solver(n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
+               k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha)
+    c = tc_inputs.Config(cfg)
+    c["n_r"] = n_r
+    u = tc_inputs.initial_state(S.radial_nodes(), c, device="cuda")
+    fwd = torch.cat([u, u], 0)
+    adj_in = tc_inputs.random_field_torch((9, n_r, cfg.m_z, cfg.m_theta), 11, "cuda")
+    adj_out = S.empty(9)
+    S.step_adjoint(fwd, adj_in, adj_out)  # allocates the work space
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        S.step_adjoint(fwd, adj_in, adj_out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    modes = cfg.m_theta * (cfg.m_z - 1)
+    ndm = cfg.m_theta * (cfg.m_z // 2)
+    alg = 21 * 16 * n_r * modes + 5 * 9 * 8 * n_r * ndm
+    S.close()
+    del S, u, fwd, adj_in, adj_out
+    torch.cuda.empty_cache()
+    ach = alg / (ms * 1e-3) / 1e9
+    return {"ms_per_adjoint_step": round(ms, 3), "algorithmic_bytes": int(alg), "achieved_GBs": round(ach, 1),
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "workload": f"production planes ({2 * cfg.m_theta}x{cfg.m_z} physical) with N_r={n_r}, FP64, mean of {reps}"}
+
+
 def cpu_baseline(cfg, u0_dev, repeats=3):
     """FP64 oracle on a bounded sample: 9 full-size radial planes of the
     nonlinear term and the predictor-corrector for the l = 0, +-1 modes at
@@ -287,6 +326,8 @@ def main():
     if not args.no_adjoint:
         print("[bench] adjoint/forward cost ratio", file=sys.stderr, flush=True)
         out["adjoint_forward_ratio"] = adjoint_ratio()
+        print("[bench] adjoint step at scale", file=sys.stderr, flush=True)
+        out["adjoint_step_at_scale"] = adjoint_step_at_scale(cfg)
     if not args.no_cpu:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, u0)
