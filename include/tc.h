@@ -79,11 +79,12 @@ typedef struct {
                          n_r = M + 1); 9 <= n_r <= 4096                      */
   int32_t m_theta;    /* stored azimuthal wavenumbers n = 0..m_theta-1        */
   int32_t m_z;        /* axial slots (even)                                   */
-  int32_t p_theta;    /* dealiased azimuthal grid; 0 -> 3*m_theta. Must be
-                         >= 3*m_theta - 2 (3/2 rule, Sec. 3.1) and a supported
-                         transform length                                     */
-  int32_t p_z;        /* dealiased axial grid; 0 -> 3*m_z/2, >= 3*m_z/2 - 2,
-                         a supported transform length                         */
+  int32_t p_theta;    /* dealiased azimuthal grid. Must be >= 3*m_theta - 2
+                         (3/2 rule, Sec. 3.1) and a supported transform length
+                         (16, 24, 32, 48, ..., 1536, 2048: 2^k and 3*2^k);
+                         0 -> the smallest supported length >= 3*m_theta - 2 */
+  int32_t p_z;        /* dealiased axial grid; >= 3*m_z/2 - 2 and a supported
+                         length; 0 -> the smallest one >= 3*m_z/2 - 2         */
   double k_theta;     /* fundamental azimuthal wavenumber (L_theta = 2pi/k_theta) */
   double k_z;         /* fundamental axial wavenumber (Gamma = 2pi/k_z)         */
   double alpha;       /* node-map parameter of eq. nodeDist; 0 = Chebyshev limit */

@@ -334,8 +334,11 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
     return TC_EINVAL;
   }
   tc_grid G = *g;
-  if (G.p_theta == 0) G.p_theta = 3 * G.m_theta;
-  if (G.p_z == 0) G.p_z = 3 * G.m_z / 2;
+  // default dealiased grid: the smallest supported length that meets the
+  // 3/2 rule (0 when the rule asks for more than the longest one, which the
+  // length check below then rejects)
+  if (G.p_theta == 0) G.p_theta = fft_length_at_least(3 * G.m_theta - 2);
+  if (G.p_z == 0) G.p_z = fft_length_at_least(3 * G.m_z / 2 - 2);
   std::string why;
   if (G.n_r < 9 || G.n_r > 4096) why = "n_r must be in [9, 4096]";
   else if (G.m_theta < 1 || G.m_z < 2 || (G.m_z % 2)) why = "m_theta >= 1 and even m_z >= 2 required";
