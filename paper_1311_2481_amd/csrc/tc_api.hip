@@ -321,6 +321,13 @@ const char* tc_last_error(const tc_ctx* ctx) {
   return ctx->err.c_str();
 }
 
+// smallest supported transform length >= L (0 if there is none)
+static int fft_length_at_least(int L) {
+  for (int x = L < 1 ? 1 : L; x <= 2048; ++x)
+    if (fft_length_supported(x)) return x;
+  return 0;
+}
+
 tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double dt, void* hip_stream,
                   tc_ctx** out) {
   g_init_error.clear();

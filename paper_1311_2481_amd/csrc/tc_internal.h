@@ -125,8 +125,6 @@ hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* in
 hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32);
 hipError_t launch_theta_adj(tc_ctx* c, int nplanes, void* inter);
 bool fft_length_supported(int L);
-// smallest supported transform length >= L (0 if there is none)
-int fft_length_at_least(int L);
 size_t inter_bytes_per_plane(const tc_ctx* c);
 
 // timing helpers (no-ops unless ctx->timing)

@@ -640,13 +640,6 @@ bool fft_length_supported(int L) {
   return false;
 }
 
-int fft_length_at_least(int L) {
-#define TC_CASE(LL) if (L <= LL) return LL;
-  TC_FFT_LENGTHS(TC_CASE)
-#undef TC_CASE
-  return 0;
-}
-
 size_t inter_bytes_per_plane(const tc_ctx* c) {
   const size_t el = (c->g.precision == TC_FP32_BULK) ? sizeof(cf) : sizeof(cd);
   return (size_t)6 * c->d.pz * c->d.mt * el;
