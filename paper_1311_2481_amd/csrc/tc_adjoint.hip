@@ -16,10 +16,11 @@
 // and the nonlinear term's adjoint (transposed transforms, see the azimuthal
 // adjoint kernel) applied to N_bar_total = 2 Ne_bar + N_bar.
 //
-// Work decomposition: one thread per (radial node, stored mode) point on a
-// 2-D grid (x: mode slot, y: node); D1^T is applied by gathering the (up to
-// 9) rows whose stencils touch a node, from fields written by an earlier
-// launch, with masks and sums of fields applied on the fly.  The banded
+// Work decomposition: one thread per (radial node, stored mode) point, in
+// tiles of consecutive slots of one node, numbered node-fastest and walked
+// per XCD (see make_slot); D1^T is applied by gathering the (up to 9) rows
+// whose stencils touch a node, from fields written by an earlier launch,
+// with masks and sums of fields applied on the fly.  The banded
 // transposed solves run the three Helmholtz operators in one launch.
 #include "tc_internal.h"
 
@@ -41,9 +42,26 @@ struct Slot {
   bool nyq, zero_mode;
 };
 
+// Work tiles are (radial node k, chunk of SLOT_BLOCK slots), numbered with k
+// fastest.  The grid is 1-D with 8 ceil(ntiles / 8) workgroups and
+// workgroup b takes tile (b % 8) ceil(ntiles / 8) + b / 8: workgroups are
+// dispatched round robin over the 8 XCDs, so each XCD walks a contiguous
+// tile range, and the workgroups that need the same slots of neighbouring
+// radial planes (the +-4-row stencils) run together and share that XCD's
+// L2.  Tiles past the end belong to padding workgroups.
+constexpr int SLOT_BLOCK = 256;
+
+__host__ __device__ inline int64_t slot_tiles(const Dims& d) {
+  return (d.S + SLOT_BLOCK - 1) / SLOT_BLOCK * (int64_t)d.n_r;
+}
+
 __device__ __forceinline__ bool make_slot(const Dims& d, Slot& q) {
-  q.idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  q.k = blockIdx.y;
+  const int64_t ntiles = slot_tiles(d);
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t id = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (id >= ntiles) return false;
+  q.k = (int)(id % d.n_r);
+  q.idx = (id / d.n_r) * SLOT_BLOCK + threadIdx.x;
   if (q.idx >= d.S) return false;
   q.s = (int)(q.idx / d.mt);
   q.n = (int)(q.idx - (int64_t)q.s * d.mt);
@@ -112,10 +130,10 @@ __global__ void k_adj_ustar(const double* __restrict__ rc, Dims d, const cd* __r
   us[2 * d.F + o] = cmi(ub[2 * d.F + o], cimul(f, q.b));
 }
 
-// From rhs_u_bar (interior rows of ru): u_bar = -(2/dt) r, u_prev_bar = r/(2dt),
-// Ne_bar = r, p_bar = grad^H r.
+// From rhs_u_bar (interior rows r of ru): u_bar = -(2/dt) r, u_prev_bar = r/(2dt),
+// p_bar = grad^H r.  (Ne_bar = r is read from ru by the pressure-RHS kernel.)
 __global__ void k_adj_rhsu(const double* __restrict__ rc, Dims d, const cd* __restrict__ ru, cd* __restrict__ u_b,
-                           cd* __restrict__ up_b, cd* __restrict__ ne_b, cd* __restrict__ p_b) {
+                           cd* __restrict__ up_b, cd* __restrict__ p_b) {
   Slot q;
   if (!make_slot(d, q)) return;
   const int M = d.n_r - 1;
@@ -126,7 +144,6 @@ __global__ void k_adj_rhsu(const double* __restrict__ rc, Dims d, const cd* __re
     const cd r = mr(c, k);
     u_b[c * d.F + o] = cs(r, -2.0 / d.dt);
     up_b[c * d.F + o] = cs(r, 0.5 / d.dt);
-    ne_b[c * d.F + o] = r;
   }
   if (q.nyq) {
     p_b[o] = cz();
@@ -139,12 +156,14 @@ __global__ void k_adj_rhsu(const double* __restrict__ rc, Dims d, const cd* __re
   p_b[o] = g;
 }
 
-// Pressure-RHS adjoint: Ne_bar -= div^H(I rp) and -(W rp)/2 on Ne+-, with W
-// the wall rows of the consistent Neumann condition (not the outer row of
-// mode (0,0)); V_r^H(W rp) = ((L+^T w)/2, (L-^T w)/2): u_bar += 2 V,
-// u_prev_bar -= V.  Also writes N_prev_bar = -Ne_bar and
+// Pressure-RHS adjoint: Ne_bar = I ru (the interior rows of rhs_u_bar)
+// minus div^H(I rp) and -(W rp)/2 on Ne+-, with W the wall rows of the
+// consistent Neumann condition (not the outer row of mode (0,0));
+// V_r^H(W rp) = ((L+^T w)/2, (L-^T w)/2): u_bar += 2 V, u_prev_bar -= V.
+// V vanishes more than HW rows from both walls, where u_bar and u_prev_bar
+// are left untouched.  Also writes N_prev_bar = -Ne_bar and
 // N_tot = 2 Ne_bar + N_bar_in.
-__global__ void k_adj_rhsp(const double* __restrict__ rc, Dims d, const cd* __restrict__ rp, cd* __restrict__ ne_b,
+__global__ void k_adj_rhsp(const double* __restrict__ rc, Dims d, const cd* __restrict__ rp, const cd* __restrict__ ru,
                            cd* __restrict__ u_b, cd* __restrict__ up_b, const cd* __restrict__ n_in,
                            cd* __restrict__ n_prev_b, cd* __restrict__ n_tot) {
   Slot q;
@@ -164,26 +183,30 @@ __global__ void k_adj_rhsp(const double* __restrict__ rc, Dims d, const cd* __re
   };
   const double ir = rc[(int64_t)k * RC_N + RC_IR];
   const double ir2 = rc[(int64_t)k * RC_N + RC_IR2];
-  cd ne[3] = {ne_b[o], ne_b[d.F + o], ne_b[2 * d.F + o]};
+  cd ne[3] = {cz(), cz(), cz()};
+  if (k != 0 && k != M)
+    for (int c = 0; c < 3; ++c) ne[c] = ru[c * d.F + o];
   const cd f = mr(k);
   const cd dt = cs(gather_t(rc, d, k, RC_W1, mr), 0.5);
   ne[0] = cmi(ne[0], cpl(dt, cs(f, 0.5 * (1.0 + q.a) * ir)));
   ne[1] = cmi(ne[1], cpl(dt, cs(f, 0.5 * (1.0 - q.a) * ir)));
   ne[2] = cpl(ne[2], cimul(f, q.b));  // -(-i b f)
-  const cd w = wr(k);
-  ne[0] = cmi(ne[0], cs(w, 0.5));
-  ne[1] = cmi(ne[1], cs(w, 0.5));
-  // L+-^T w = D2^T w + D1^T(w / r) - (a^2/r^2 + b^2 + (1 +- 2a)/r^2) w
-  const cd t2 = gather_t(rc, d, k, RC_W2, wr);
-  const cd t1 = gather_t(rc, d, k, RC_W1, [&](int i) { return cs(wr(i), rc[(int64_t)i * RC_N + RC_IR]); });
-  const cd base = cpl(t2, t1);
-  const double dd = q.a * q.a * ir2 + q.b * q.b;
-  const cd vp = cs(cmi(base, cs(w, dd + (1.0 + 2.0 * q.a) * ir2)), 0.5);
-  const cd vm = cs(cmi(base, cs(w, dd + (1.0 - 2.0 * q.a) * ir2)), 0.5);
-  u_b[o] = cpl(u_b[o], cs(vp, 2.0));
-  u_b[d.F + o] = cpl(u_b[d.F + o], cs(vm, 2.0));
-  up_b[o] = cmi(up_b[o], vp);
-  up_b[d.F + o] = cmi(up_b[d.F + o], vm);
+  if (k <= HW || k >= M - HW) {
+    const cd w = wr(k);
+    ne[0] = cmi(ne[0], cs(w, 0.5));
+    ne[1] = cmi(ne[1], cs(w, 0.5));
+    // L+-^T w = D2^T w + D1^T(w / r) - (a^2/r^2 + b^2 + (1 +- 2a)/r^2) w
+    const cd t2 = gather_t(rc, d, k, RC_W2, wr);
+    const cd t1 = gather_t(rc, d, k, RC_W1, [&](int i) { return cs(wr(i), rc[(int64_t)i * RC_N + RC_IR]); });
+    const cd base = cpl(t2, t1);
+    const double dd = q.a * q.a * ir2 + q.b * q.b;
+    const cd vp = cs(cmi(base, cs(w, dd + (1.0 + 2.0 * q.a) * ir2)), 0.5);
+    const cd vm = cs(cmi(base, cs(w, dd + (1.0 - 2.0 * q.a) * ir2)), 0.5);
+    u_b[o] = cpl(u_b[o], cs(vp, 2.0));
+    u_b[d.F + o] = cpl(u_b[d.F + o], cs(vm, 2.0));
+    up_b[o] = cmi(up_b[o], vp);
+    up_b[d.F + o] = cmi(up_b[d.F + o], vm);
+  }
   for (int c = 0; c < 3; ++c) {
     n_prev_b[c * d.F + o] = cd{-ne[c].x, -ne[c].y};
     n_tot[c * d.F + o] = cpl(cs(ne[c], 2.0), n_in[c * d.F + o]);
@@ -241,8 +264,8 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
     const char* b = static_cast<const char*>(adj_out);
     if (a < b + 9 * FB && b < a + 9 * FB) return fail(c, TC_EINVAL, "adj_in and adj_out overlap");
   }
-  // work space: 16 fields + the 9-field transform buffer (double)
-  const int NW = 16;
+  // work space: 13 fields + the 9-field transform buffer (double)
+  const int NW = 13;
   const size_t inter9 = (size_t)9 * d.pz * d.mt * sizeof(cd) * d.n_r;
   const size_t need = NW * FB + inter9;
   if (c->aux_bytes < need) {
@@ -266,10 +289,9 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   cd* rphi = w + 1 * F;
   cd* us = w + 2 * F;    // 3
   cd* ru = w + 5 * F;    // 3
-  cd* neb = w + 8 * F;   // 3
-  cd* pb = w + 11 * F;
-  cd* rp = w + 12 * F;
-  cd* ntot = w + 13 * F;  // 3 (13..15), then the 6 nonlinear cotangents reuse us/ru
+  cd* pb = w + 8 * F;
+  cd* rp = w + 9 * F;
+  cd* ntot = w + 10 * F;  // 3 (10..12), then the 6 nonlinear cotangents reuse us/ru
   cd* nl6 = us;           // 6 fields: us (3) + ru (3), free by then
   void* inter = w + NW * F;
 
@@ -282,7 +304,7 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   cd* out_up = out + 3 * F;
   cd* out_np = out + 6 * F;
 
-  const dim3 blk(256), grd((unsigned)((d.S + 255) / 256), (unsigned)d.n_r);
+  const dim3 blk(SLOT_BLOCK), grd((unsigned)(8 * ((slot_tiles(d) + 7) / 8)));
   hipStream_t st = c->stream;
   hipError_t e;
 #define TC_TRY(x) \
@@ -297,11 +319,11 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   hipLaunchKernelGGL(k_adj_ustar, grd, blk, 0, st, c->rc_dev, d, ubn, rphi, us);
   TC_TRY(hipGetLastError());
   TC_TRY(launch_solve_t(c, OP_HP, 3, us, ru));
-  hipLaunchKernelGGL(k_adj_rhsu, grd, blk, 0, st, c->rc_dev, d, ru, out_u, out_up, neb, pb);
+  hipLaunchKernelGGL(k_adj_rhsu, grd, blk, 0, st, c->rc_dev, d, ru, out_u, out_up, pb);
   TC_TRY(hipGetLastError());
   // pressure predictor, transposed
   TC_TRY(launch_solve_t(c, OP_P, 1, pb, rp));
-  hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, neb, out_u, out_up, nin, out_np, ntot);
+  hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, ru, out_u, out_up, nin, out_np, ntot);
   TC_TRY(hipGetLastError());
   // nonlinear term, transposed: forward fields u, omega(u) and the cotangent N_tot
   TC_TRY(launch_curl(c, u, c->omega));
