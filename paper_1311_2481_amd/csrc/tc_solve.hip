@@ -228,6 +228,10 @@ __device__ __forceinline__ bool make_lane1(const Dims& d, Lane1& L) {
   const double *__restrict__ rc, const double *__restrict__ fac, Dims d, const cd *__restrict__ u, const cd *up, \
       const cd *__restrict__ N, cd *Np, cd *un, cd *p, int want_p
 
+// Each sweep runs in three phases (rows that only enter the lagging
+// stencil window, rows that do both parts, rows that only leave it), so the
+// middle phase has no row-range branches and all of a row's loads are issued
+// together at the top of its iteration: a lane waits for memory once per row.
 __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
@@ -241,63 +245,97 @@ __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
   cd acc[NB9], yw[4], ner0 = cz(), nerM = cz();
   for (int k = 0; k < NB9; ++k) acc[k] = cz();
   for (int q = 0; q < 4; ++q) yw[q] = cz();
-  for (int j = 0; j <= M + HW; ++j) {
-    if (j <= M) {
-      const double ir = rc[(int64_t)j * RC_N + RC_IR];
-      const int64_t o = j * S + L.o;
-      if (j <= HW || j >= M - HW) {
-        const cd vp = csub(cmuls(u[o], 2.0), up[o]);
-        const cd vm = csub(cmuls(u[F + o], 2.0), up[F + o]);
-        const cd sum = cadd(vp, vm), dif = csub(vp, vm);
+  auto load_row = [&](int j, cd (&nv)[3], cd (&pv)[3]) {
+    const int64_t o = j * S + L.o;
 #pragma unroll
-        for (int wsel = 0; wsel < 2; ++wsel) {
-          const int jw = wsel ? M : 0;
-          const int k = j - jw + HW;
-          if (k < 0 || k >= NB9) continue;
-          const double* R = rc + (int64_t)jw * RC_N;
-          cd t = cmuls(sum, 0.5 * (R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR]));
-          if (k == HW) {
-            t = cfma(t, 0.5 * (-(a * a + 1.0) * R[RC_IR2] - L.b * L.b), sum);
-            t = cfma(t, -a * R[RC_IR2], dif);
-          }
-          if (wsel) bcM = cadd(bcM, t); else bc0 = cadd(bc0, t);
+    for (int c = 0; c < 3; ++c) {
+      nv[c] = N[c * F + o];
+      pv[c] = Np[c * F + o];
+    }
+  };
+  auto load_fac = [&](int i, double (&fl)[4]) {
+    const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+  };
+  // row j enters: Ne = 2 N^i - N^{i-1} (kept in N_prev), wall terms, D1 scatter
+  auto feed = [&](int j, const cd (&nv)[3], const cd (&pv)[3]) {
+    const double ir = rc[(int64_t)j * RC_N + RC_IR];
+    const int64_t o = j * S + L.o;
+    if (j <= HW || j >= M - HW) {
+      const cd vp = csub(cmuls(u[o], 2.0), up[o]);
+      const cd vm = csub(cmuls(u[F + o], 2.0), up[F + o]);
+      const cd sum = cadd(vp, vm), dif = csub(vp, vm);
+#pragma unroll
+      for (int wsel = 0; wsel < 2; ++wsel) {
+        const int jw = wsel ? M : 0;
+        const int k = j - jw + HW;
+        if (k < 0 || k >= NB9) continue;
+        const double* R = rc + (int64_t)jw * RC_N;
+        cd t = cmuls(sum, 0.5 * (R[RC_W2 + k] + R[RC_W1 + k] * R[RC_IR]));
+        if (k == HW) {
+          t = cfma(t, 0.5 * (-(a * a + 1.0) * R[RC_IR2] - L.b * L.b), sum);
+          t = cfma(t, -a * R[RC_IR2], dif);
         }
+        if (wsel) bcM = cadd(bcM, t); else bc0 = cadd(bc0, t);
       }
-      const cd ep = csub(cmuls(N[o], 2.0), Np[o]);
-      const cd em = csub(cmuls(N[F + o], 2.0), Np[F + o]);
-      const cd ez = csub(cmuls(N[2 * F + o], 2.0), Np[2 * F + o]);
-      Np[o] = ep;
-      Np[F + o] = em;
-      Np[2 * F + o] = ez;
-      const cd er = cmuls(cadd(ep, em), 0.5);
-      if (j == 0) ner0 = er;
-      if (j == M) nerM = er;
-      // D1 scatter: row j feeds rows i = j-4..j+4 (slot k = i - j + 4)
-#pragma unroll
-      for (int k = 0; k < NB9; ++k) {
-        const int i = j - HW + k;
-        if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], er);
-      }
-      cd l = cmuls(er, ir);
-      l = cfma(l, 0.5 * a * ir, csub(ep, em));
-      l = cadd(l, cimul(ez, L.b));
-      acc[HW] = cadd(acc[HW], l);
     }
-    const int i = j - HW;
-    if (i >= 0) {
-      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
-      cd rhs;
-      if (i == 0) rhs = cmuls(csub(bc0, ner0), d.s0);
-      else if (i == M) rhs = L.zero_mode ? cz() : cmuls(csub(bcM, nerM), d.sM);
-      else rhs = cd{-acc[0].x, -acc[0].y};
+    const cd ep = csub(cmuls(nv[0], 2.0), pv[0]);
+    const cd em = csub(cmuls(nv[1], 2.0), pv[1]);
+    const cd ez = csub(cmuls(nv[2], 2.0), pv[2]);
+    Np[o] = ep;
+    Np[F + o] = em;
+    Np[2 * F + o] = ez;
+    const cd er = cmuls(cadd(ep, em), 0.5);
+    if (j == 0) ner0 = er;
+    if (j == M) nerM = er;
+    // D1 scatter: row j feeds rows i = j-4..j+4 (slot k = i - j + 4)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yw[q]);
-      for (int q = 3; q >= 1; --q) yw[q] = yw[q - 1];
-      yw[0] = rhs;
-      p[i * S + L.o] = rhs;
+    for (int k = 0; k < NB9; ++k) {
+      const int i = j - HW + k;
+      if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], er);
     }
+    cd l = cmuls(er, ir);
+    l = cfma(l, 0.5 * a * ir, csub(ep, em));
+    l = cadd(l, cimul(ez, L.b));
+    acc[HW] = cadd(acc[HW], l);
+  };
+  // row i leaves the window: forward sweep of P -> y_p (in p)
+  auto solve = [&](int i, const double (&fl)[4]) {
+    cd rhs;
+    if (i == 0) rhs = cmuls(csub(bc0, ner0), d.s0);
+    else if (i == M) rhs = L.zero_mode ? cz() : cmuls(csub(bcM, nerM), d.sM);
+    else rhs = cd{-acc[0].x, -acc[0].y};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, fl[q], yw[q]);
+    for (int q = 3; q >= 1; --q) yw[q] = yw[q - 1];
+    yw[0] = rhs;
+    p[i * S + L.o] = rhs;
+  };
+  auto shift = [&]() {
     for (int k = 0; k < NB9 - 1; ++k) acc[k] = acc[k + 1];
     acc[NB9 - 1] = cz();
+  };
+  for (int j = 0; j < HW; ++j) {
+    cd nv[3], pv[3];
+    load_row(j, nv, pv);
+    feed(j, nv, pv);
+    shift();
+  }
+  for (int j = HW; j <= M; ++j) {
+    cd nv[3], pv[3];
+    double fl[4];
+    load_row(j, nv, pv);
+    load_fac(j - HW, fl);
+    feed(j, nv, pv);
+    solve(j - HW, fl);
+    shift();
+  }
+  for (int j = M + 1; j <= M + HW; ++j) {
+    double fl[4];
+    load_fac(j - HW, fl);
+    solve(j - HW, fl);
+    shift();
   }
 }
 
@@ -312,21 +350,34 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
   for (int k = 0; k < NB9; ++k) pw[k] = cz();
   for (int o = 0; o < 3; ++o)
     for (int q = 0; q < 4; ++q) zw[o][q] = cz();
-  for (int jj = M; jj >= -HW; --jj) {
-    for (int k = NB9 - 1; k >= 1; --k) pw[k] = pw[k - 1];
-    if (jj >= 0) {
-      const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
-      cd y = p[jj * S + L.o];
+  auto load_back = [&](int jj, cd& y, double (&fu)[5]) {
+    const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
 #pragma unroll
-      for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], pw[c]);
-      y = cmuls(y, Fp[(int64_t)4 * d.ndm]);
-      pw[0] = y;
-      if (want_p) p[jj * S + L.o] = y;
-    } else {
-      pw[0] = cz();
+    for (int c = 0; c < 5; ++c) fu[c] = Fp[(int64_t)(4 + c) * d.ndm];
+    y = p[jj * S + L.o];
+  };
+  auto load_h = [&](int i, cd (&ne)[3], cd (&uu)[3], cd (&uq)[3], double (&fh)[3][4]) {
+    const int64_t o = i * S + L.o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ne[c] = Np[c * F + o];
+      uu[c] = u[c * F + o];
+      uq[c] = up[c * F + o];
+      const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fh[c][q] = Fh[(int64_t)q * d.ndm];
     }
-    const int i = jj + HW;
-    if (i > M) continue;
+  };
+  // back-substitution of p* at row jj
+  auto back = [&](int jj, cd y, const double (&fu)[5]) {
+#pragma unroll
+    for (int c = 1; c <= 4; ++c) y = cnfma(y, fu[c], pw[c]);
+    y = cmuls(y, fu[0]);
+    pw[0] = y;
+    if (want_p) p[jj * S + L.o] = y;
+  };
+  // RHS of the Helmholtz problems at row i and their first (descending) sweep
+  auto hrow = [&](int i, const cd (&ne)[3], const cd (&uu)[3], const cd (&uq)[3], const double (&fh)[3][4]) {
     const double* R = rc + (int64_t)i * RC_N;
     const double ir = R[RC_IR];
     cd rhs[3];
@@ -340,12 +391,10 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
 #pragma unroll
       for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], pw[k]);
       const cd pi = pw[HW];
-      const int64_t o = i * S + L.o;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const cd ne = Np[c * F + o];
-        const cd ut = csub(cmuls(u[c * F + o], 4.0), up[c * F + o]);
-        cd r = cd{ne.x - ut.x * c_dt, ne.y - ut.y * c_dt};
+        const cd ut = csub(cmuls(uu[c], 4.0), uq[c]);
+        cd r = cd{ne[c].x - ut.x * c_dt, ne[c].y - ut.y * c_dt};
         if (c == 0) r = cadd(r, cnfma(d1, a * ir, pi));
         if (c == 1) r = cadd(r, cfma(d1, a * ir, pi));
         if (c == 2) r = cadd(r, cimul(pi, L.b));
@@ -354,14 +403,40 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
       cd z = rhs[c];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) z = cnfma(z, Fh[(int64_t)q * d.ndm], zw[c][q]);
+      for (int q = 0; q < 4; ++q) z = cnfma(z, fh[c][q], zw[c][q]);
       for (int q = 3; q >= 1; --q) zw[c][q] = zw[c][q - 1];
       zw[c][0] = z;
       un[c * F + i * S + L.o] = z;
     }
+  };
+  auto shift = [&]() {
+    for (int k = NB9 - 1; k >= 1; --k) pw[k] = pw[k - 1];
+  };
+  for (int jj = M; jj > M - HW; --jj) {
+    cd y;
+    double fu[5];
+    load_back(jj, y, fu);
+    shift();
+    back(jj, y, fu);
+  }
+  for (int jj = M - HW; jj >= 0; --jj) {
+    cd y, ne[3], uu[3], uq[3];
+    double fu[5], fh[3][4];
+    load_back(jj, y, fu);
+    load_h(jj + HW, ne, uu, uq, fh);
+    shift();
+    back(jj, y, fu);
+    hrow(jj + HW, ne, uu, uq, fh);
+  }
+  for (int jj = -1; jj >= -HW; --jj) {
+    cd ne[3], uu[3], uq[3];
+    double fh[3][4];
+    load_h(jj + HW, ne, uu, uq, fh);
+    shift();
+    pw[0] = cz();
+    hrow(jj + HW, ne, uu, uq, fh);
   }
 }
 
@@ -376,46 +451,80 @@ __global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
     for (int q = 0; q < 4; ++q) xw[c][q] = cz();
   for (int k = 0; k < NB9; ++k) acc[k] = cz();
   for (int q = 0; q < 4; ++q) yp[q] = cz();
-  for (int j = 0; j <= M + HW; ++j) {
-    if (j <= M) {
-      const double ir = rc[(int64_t)j * RC_N + RC_IR];
-      cd xs[3];
+  auto load_row = [&](int j, cd (&zv)[3], double (&fh)[3][5]) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double* Fh = facp(fac, d, OP_HP + c, j) + L.dm;
-        const int64_t o = c * F + j * S + L.o;
-        cd y = un[o];
+    for (int c = 0; c < 3; ++c) {
+      const double* Fh = facp(fac, d, OP_HP + c, j) + L.dm;
 #pragma unroll
-        for (int q = 1; q <= 4; ++q) y = cnfma(y, Fh[(int64_t)(4 + q) * d.ndm], xw[c][q - 1]);
-        y = cmuls(y, Fh[(int64_t)4 * d.ndm]);
-        for (int q = 3; q >= 1; --q) xw[c][q] = xw[c][q - 1];
-        xw[c][0] = y;
-        un[o] = y;
-        xs[c] = y;
-      }
-      const cd ur = cmuls(cadd(xs[0], xs[1]), 0.5);
-#pragma unroll
-      for (int k = 0; k < NB9; ++k) {
-        const int i = j - HW + k;
-        if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], ur);
-      }
-      cd l = cmuls(ur, ir);
-      l = cfma(l, 0.5 * a * ir, csub(xs[0], xs[1]));
-      l = cadd(l, cimul(xs[2], L.b));
-      acc[HW] = cadd(acc[HW], l);
+      for (int q = 0; q < 5; ++q) fh[c][q] = Fh[(int64_t)(4 + q) * d.ndm];
+      zv[c] = un[c * F + j * S + L.o];
     }
-    const int i = j - HW;
-    if (i >= 0) {
-      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
-      cd rhs = (i != 0 && i != M) ? acc[0] : cz();
+  };
+  auto load_fac = [&](int i, double (&fl)[4]) {
+    const double* Fp = facp(fac, d, OP_P, i) + L.dm;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, Fp[(int64_t)q * d.ndm], yp[q]);
-      for (int q = 3; q >= 1; --q) yp[q] = yp[q - 1];
-      yp[0] = rhs;
-      Np[i * S + L.o] = rhs;
+    for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+  };
+  // row j: u* by the second Helmholtz sweep, then its divergence scattered
+  auto feed = [&](int j, const cd (&zv)[3], const double (&fh)[3][5]) {
+    const double ir = rc[(int64_t)j * RC_N + RC_IR];
+    cd xs[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cd y = zv[c];
+#pragma unroll
+      for (int q = 1; q <= 4; ++q) y = cnfma(y, fh[c][q], xw[c][q - 1]);
+      y = cmuls(y, fh[c][0]);
+      for (int q = 3; q >= 1; --q) xw[c][q] = xw[c][q - 1];
+      xw[c][0] = y;
+      un[c * F + j * S + L.o] = y;
+      xs[c] = y;
     }
+    const cd ur = cmuls(cadd(xs[0], xs[1]), 0.5);
+#pragma unroll
+    for (int k = 0; k < NB9; ++k) {
+      const int i = j - HW + k;
+      if (i >= 0 && i <= M) acc[k] = cfma(acc[k], rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - k)], ur);
+    }
+    cd l = cmuls(ur, ir);
+    l = cfma(l, 0.5 * a * ir, csub(xs[0], xs[1]));
+    l = cadd(l, cimul(xs[2], L.b));
+    acc[HW] = cadd(acc[HW], l);
+  };
+  // row i: forward sweep of P for phi -> y_phi (in N_prev[0])
+  auto solve = [&](int i, const double (&fl)[4]) {
+    cd rhs = (i != 0 && i != M) ? acc[0] : cz();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rhs = cnfma(rhs, fl[q], yp[q]);
+    for (int q = 3; q >= 1; --q) yp[q] = yp[q - 1];
+    yp[0] = rhs;
+    Np[i * S + L.o] = rhs;
+  };
+  auto shift = [&]() {
     for (int k = 0; k < NB9 - 1; ++k) acc[k] = acc[k + 1];
     acc[NB9 - 1] = cz();
+  };
+  for (int j = 0; j < HW; ++j) {
+    cd zv[3];
+    double fh[3][5];
+    load_row(j, zv, fh);
+    feed(j, zv, fh);
+    shift();
+  }
+  for (int j = HW; j <= M; ++j) {
+    cd zv[3];
+    double fh[3][5], fl[4];
+    load_row(j, zv, fh);
+    load_fac(j - HW, fl);
+    feed(j, zv, fh);
+    solve(j - HW, fl);
+    shift();
+  }
+  for (int j = M + 1; j <= M + HW; ++j) {
+    double fl[4];
+    load_fac(j - HW, fl);
+    solve(j - HW, fl);
+    shift();
   }
 }
 
@@ -429,19 +538,26 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
   const bool nyq_lane = (L.dm < d.mt) && (threadIdx.x < 32);  // |l| = 0, +l half: clears the empty slot
   cd fw[NB9];
   for (int k = 0; k < NB9; ++k) fw[k] = cz();
-  for (int jj = M; jj >= -HW; --jj) {
-    for (int k = NB9 - 1; k >= 1; --k) fw[k] = fw[k - 1];
-    if (jj >= 0) {
-      const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
-      cd y = Np[jj * S + L.o];
+  auto load_back = [&](int jj, cd& y, double (&fu)[5]) {
+    const double* Fp = facp(fac, d, OP_P, jj) + L.dm;
 #pragma unroll
-      for (int c = 1; c <= 4; ++c) y = cnfma(y, Fp[(int64_t)(4 + c) * d.ndm], fw[c]);
-      fw[0] = cmuls(y, Fp[(int64_t)4 * d.ndm]);
-    } else {
-      fw[0] = cz();
-    }
-    const int i = jj + HW;
-    if (i > M) continue;
+    for (int c = 0; c < 5; ++c) fu[c] = Fp[(int64_t)(4 + c) * d.ndm];
+    y = Np[jj * S + L.o];
+  };
+  auto load_corr = [&](int i, cd (&us)[3], cd& pv) {
+    const int64_t o = i * S + L.o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) us[c] = un[c * F + o];
+    pv = want_p ? p[o] : cz();
+  };
+  // back-substitution of phi at row jj
+  auto back = [&](cd y, const double (&fu)[5]) {
+#pragma unroll
+    for (int c = 1; c <= 4; ++c) y = cnfma(y, fu[c], fw[c]);
+    fw[0] = cmuls(y, fu[0]);
+  };
+  // correction and pressure update at row i
+  auto correct = [&](int i, const cd (&us)[3], cd pv) {
     const double* R = rc + (int64_t)i * RC_N;
     const double ir = R[RC_IR];
     cd d1 = cz();
@@ -449,15 +565,41 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k]);
     const cd ph = fw[HW];
     const int64_t o = i * S + L.o;
-    un[o] = csub(un[o], cnfma(d1, a * ir, ph));
-    un[F + o] = csub(un[F + o], cfma(d1, a * ir, ph));
-    un[2 * F + o] = csub(un[2 * F + o], cimul(ph, L.b));
-    if (want_p) p[o] = cfma(p[o], c_p, ph);
+    un[o] = csub(us[0], cnfma(d1, a * ir, ph));
+    un[F + o] = csub(us[1], cfma(d1, a * ir, ph));
+    un[2 * F + o] = csub(us[2], cimul(ph, L.b));
+    if (want_p) p[o] = cfma(pv, c_p, ph);
     if (nyq_lane) {
       const int64_t on = i * S + (int64_t)d.nyq * d.mt + (L.dm % d.mt);
       un[on] = cz(); un[F + on] = cz(); un[2 * F + on] = cz();
       if (want_p) p[on] = cz();
     }
+  };
+  auto shift = [&]() {
+    for (int k = NB9 - 1; k >= 1; --k) fw[k] = fw[k - 1];
+  };
+  for (int jj = M; jj > M - HW; --jj) {
+    cd y;
+    double fu[5];
+    load_back(jj, y, fu);
+    shift();
+    back(y, fu);
+  }
+  for (int jj = M - HW; jj >= 0; --jj) {
+    cd y, us[3], pv;
+    double fu[5];
+    load_back(jj, y, fu);
+    load_corr(jj + HW, us, pv);
+    shift();
+    back(y, fu);
+    correct(jj + HW, us, pv);
+  }
+  for (int jj = -1; jj >= -HW; --jj) {
+    cd us[3], pv;
+    load_corr(jj + HW, us, pv);
+    shift();
+    fw[0] = cz();
+    correct(jj + HW, us, pv);
   }
 }
 
