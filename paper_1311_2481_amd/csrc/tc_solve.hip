@@ -228,10 +228,14 @@ __device__ __forceinline__ bool make_lane1(const Dims& d, Lane1& L) {
   const double *__restrict__ rc, const double *__restrict__ fac, Dims d, const cd *__restrict__ u, const cd *up, \
       const cd *__restrict__ N, cd *Np, cd *un, cd *p, int want_p
 
+#ifndef PC_CH
+#define PC_CH 4
+#endif
 // Each sweep runs in three phases (rows that only enter the lagging
 // stencil window, rows that do both parts, rows that only leave it), so the
 // middle phase has no row-range branches and all of a row's loads are issued
 // together at the top of its iteration: a lane waits for memory once per row.
+template <int CH>
 __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
@@ -322,14 +326,42 @@ __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
     feed(j, nv, pv);
     shift();
   }
-  for (int j = HW; j <= M; ++j) {
-    cd nv[3], pv[3];
-    double fl[4];
-    load_row(j, nv, pv);
-    load_fac(j - HW, fl);
-    feed(j, nv, pv);
-    solve(j - HW, fl);
-    shift();
+  if constexpr (CH == 1) {
+    for (int j = HW; j <= M; ++j) {
+      cd nv[3], pv[3];
+      double fl[4];
+      load_row(j, nv, pv);
+      load_fac(j - HW, fl);
+      feed(j, nv, pv);
+      solve(j - HW, fl);
+      shift();
+    }
+  } else {
+    int j = HW;
+    for (; j + CH - 1 <= M; j += CH) {
+      cd nv[CH][3], pv[CH][3];
+      double fl[CH][4];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        load_row(j + r, nv[r], pv[r]);
+        load_fac(j + r - HW, fl[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        feed(j + r, nv[r], pv[r]);
+        solve(j + r - HW, fl[r]);
+        shift();
+      }
+    }
+    for (; j <= M; ++j) {
+      cd nv[3], pv[3];
+      double fl[4];
+      load_row(j, nv, pv);
+      load_fac(j - HW, fl);
+      feed(j, nv, pv);
+      solve(j - HW, fl);
+      shift();
+    }
   }
   for (int j = M + 1; j <= M + HW; ++j) {
     double fl[4];
@@ -339,6 +371,7 @@ __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
   }
 }
 
+template <int CH>
 __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
@@ -421,14 +454,42 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
     shift();
     back(jj, y, fu);
   }
-  for (int jj = M - HW; jj >= 0; --jj) {
-    cd y, ne[3], uu[3], uq[3];
-    double fu[5], fh[3][4];
-    load_back(jj, y, fu);
-    load_h(jj + HW, ne, uu, uq, fh);
-    shift();
-    back(jj, y, fu);
-    hrow(jj + HW, ne, uu, uq, fh);
+  if constexpr (CH == 1) {
+    for (int jj = M - HW; jj >= 0; --jj) {
+      cd y, ne[3], uu[3], uq[3];
+      double fu[5], fh[3][4];
+      load_back(jj, y, fu);
+      load_h(jj + HW, ne, uu, uq, fh);
+      shift();
+      back(jj, y, fu);
+      hrow(jj + HW, ne, uu, uq, fh);
+    }
+  } else {
+    int jj = M - HW;
+    for (; jj - (CH - 1) >= 0; jj -= CH) {
+      cd y[CH], ne[CH][3], uu[CH][3], uq[CH][3];
+      double fu[CH][5], fh[CH][3][4];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        load_back(jj - r, y[r], fu[r]);
+        load_h(jj - r + HW, ne[r], uu[r], uq[r], fh[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        shift();
+        back(jj - r, y[r], fu[r]);
+        hrow(jj - r + HW, ne[r], uu[r], uq[r], fh[r]);
+      }
+    }
+    for (; jj >= 0; --jj) {
+      cd y, ne[3], uu[3], uq[3];
+      double fu[5], fh[3][4];
+      load_back(jj, y, fu);
+      load_h(jj + HW, ne, uu, uq, fh);
+      shift();
+      back(jj, y, fu);
+      hrow(jj + HW, ne, uu, uq, fh);
+    }
   }
   for (int jj = -1; jj >= -HW; --jj) {
     cd ne[3], uu[3], uq[3];
@@ -440,6 +501,7 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
   }
 }
 
+template <int CH>
 __global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
@@ -511,14 +573,42 @@ __global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
     feed(j, zv, fh);
     shift();
   }
-  for (int j = HW; j <= M; ++j) {
-    cd zv[3];
-    double fh[3][5], fl[4];
-    load_row(j, zv, fh);
-    load_fac(j - HW, fl);
-    feed(j, zv, fh);
-    solve(j - HW, fl);
-    shift();
+  if constexpr (CH == 1) {
+    for (int j = HW; j <= M; ++j) {
+      cd zv[3];
+      double fh[3][5], fl[4];
+      load_row(j, zv, fh);
+      load_fac(j - HW, fl);
+      feed(j, zv, fh);
+      solve(j - HW, fl);
+      shift();
+    }
+  } else {
+    int j = HW;
+    for (; j + CH - 1 <= M; j += CH) {
+      cd zv[CH][3];
+      double fh[CH][3][5], fl[CH][4];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        load_row(j + r, zv[r], fh[r]);
+        load_fac(j + r - HW, fl[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        feed(j + r, zv[r], fh[r]);
+        solve(j + r - HW, fl[r]);
+        shift();
+      }
+    }
+    for (; j <= M; ++j) {
+      cd zv[3];
+      double fh[3][5], fl[4];
+      load_row(j, zv, fh);
+      load_fac(j - HW, fl);
+      feed(j, zv, fh);
+      solve(j - HW, fl);
+      shift();
+    }
   }
   for (int j = M + 1; j <= M + HW; ++j) {
     double fl[4];
@@ -528,6 +618,7 @@ __global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
   }
 }
 
+template <int CH>
 __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
@@ -585,14 +676,42 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     shift();
     back(y, fu);
   }
-  for (int jj = M - HW; jj >= 0; --jj) {
-    cd y, us[3], pv;
-    double fu[5];
-    load_back(jj, y, fu);
-    load_corr(jj + HW, us, pv);
-    shift();
-    back(y, fu);
-    correct(jj + HW, us, pv);
+  if constexpr (CH == 1) {
+    for (int jj = M - HW; jj >= 0; --jj) {
+      cd y, us[3], pv;
+      double fu[5];
+      load_back(jj, y, fu);
+      load_corr(jj + HW, us, pv);
+      shift();
+      back(y, fu);
+      correct(jj + HW, us, pv);
+    }
+  } else {
+    int jj = M - HW;
+    for (; jj - (CH - 1) >= 0; jj -= CH) {
+      cd y[CH], us[CH][3], pv[CH];
+      double fu[CH][5];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        load_back(jj - r, y[r], fu[r]);
+        load_corr(jj - r + HW, us[r], pv[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        shift();
+        back(y[r], fu[r]);
+        correct(jj - r + HW, us[r], pv[r]);
+      }
+    }
+    for (; jj >= 0; --jj) {
+      cd y, us[3], pv;
+      double fu[5];
+      load_back(jj, y, fu);
+      load_corr(jj + HW, us, pv);
+      shift();
+      back(y, fu);
+      correct(jj + HW, us, pv);
+    }
   }
   for (int jj = -1; jj >= -HW; --jj) {
     cd us[3], pv;
@@ -721,7 +840,15 @@ hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
                      int want_p) {
   const int blocks = (c->d.ndm + 31) / 32;
-  for (auto* k : {k_pc1, k_pc2, k_pc3, k_pc4}) {
+  // Few waves (fewer than 2 per SIMD): too few to hide memory latency, so
+  // each lane loads PC_CH rows before working through them; otherwise one
+  // row at a time, which keeps the register count (and the occupancy that
+  // saturates HBM on large grids) down.
+  const bool chunked = blocks < 2 * 4 * 256;
+  using K = void (*)(TC_PC_ARGS);
+  const K ks[2][4] = {{k_pc1<1>, k_pc2<1>, k_pc3<1>, k_pc4<1>},
+                      {k_pc1<PC_CH>, k_pc2<PC_CH>, k_pc3<PC_CH>, k_pc4<PC_CH>}};
+  for (const K k : ks[chunked ? 1 : 0]) {
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, u, u_prev, N, N_prev,
                        u_next, p, want_p);
     const hipError_t e = hipGetLastError();
