@@ -95,6 +95,7 @@ def run_gpu(cfg, precision, steps, warmup, u0):
     S = Solver(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
                k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha, precision=precision)
     S.set_state(u0)
+    cfl0 = S.diag()["cfl"]  # outside the timed region
     S.step(warmup)
     torch.cuda.synchronize()
     S.set_timing(True)
@@ -110,7 +111,7 @@ def run_gpu(cfg, precision, steps, warmup, u0):
     S.close()
     del S
     torch.cuda.empty_cache()
-    return dict(seconds=dt, times=times, finite=finite, diag=diag, mem=mem)
+    return dict(seconds=dt, times=times, finite=finite, diag=diag, mem=mem, cfl0=cfl0)
 
 
 def adjoint_ratio(repeats=3):
@@ -309,7 +310,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload_label(cfg, args.workload), "grid_points_per_step": pts},
         "grid_pt_updates_per_s": round(sps * pts, 1),
-        "finite_after_run": f64["finite"],
+        "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3),
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
         "roofline": roof,

@@ -66,3 +66,37 @@ def wall_slip(prob, u, wall=0):
     uz[prob.nyq] = 0.0
     ms = np.sum(c * (np.abs(ut) ** 2 + np.abs(uz) ** 2))
     return np.sqrt(ms) / abs(Re)
+
+
+def cfl_bound(prob, u):
+    """Upper bound of the advective CFL number of a state,
+
+        dt max_j max_(theta, z) ( |u_r|/dr_j + |u_theta|/(r_j dtheta) + |u_z|/dz ),
+
+    on the radial nodes, with dr_j the distance from node j to its nearer
+    neighbour and dtheta = 2 pi / (k_theta 2 m_theta), dz = 2 pi / (k_z m_z)
+    the spacings of the physical grid (2 m_theta, m_z) that the stored modes
+    resolve.  The maximum over a (theta, z) plane is replaced by its bound
+    for a real field, max |f| <= sum_{l, n} c_n |f_ln| (c_0 = 1, c_n = 2:
+    the n < 0 half is the conjugate of the stored one), taken per velocity
+    component.  This is a diagnostic of the time step's explicit limit; the
+    paper discusses that limit in Sec. 5.3 and 5.5 without a formula.
+    """
+    ur = 0.5 * (u[0] + u[1])
+    ut = -0.5j * (u[0] - u[1])
+    uz = u[2]
+    c = np.full(prob.m_theta, 2.0)
+    c[0] = 1.0
+
+    def plane_bound(f):
+        a = np.abs(f)
+        a[:, prob.nyq, :] = 0.0
+        return np.einsum("jsn,n->j", a, c)
+
+    r = prob.r
+    h = np.diff(r)
+    dr = np.minimum(np.concatenate([h, [np.inf]]), np.concatenate([[np.inf], h]))
+    dth = 2.0 * np.pi / (prob.k_theta * 2 * prob.m_theta)
+    dz = 2.0 * np.pi / (prob.k_z * prob.m_z)
+    rate = plane_bound(ur) / dr + plane_bound(ut) / (r * dth) + plane_bound(uz) / dz
+    return prob.dt * float(np.max(rate))

@@ -178,9 +178,10 @@ class Solver:
         return g
 
     def diag(self):
-        out = np.zeros(5)
+        out = np.zeros(6)
         self._check(self.lib.tc_get_diag(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return dict(energy=out[0], perturbation_energy=out[1], max_div=out[2], slip=out[3], steps=int(out[4]))
+        return dict(energy=out[0], perturbation_energy=out[1], max_div=out[2], slip=out[3], cfl=out[4],
+                    steps=int(out[5]))
 
     def check_finite(self):
         st = self.lib.tc_check_finite(self.ctx)

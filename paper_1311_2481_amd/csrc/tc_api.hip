@@ -247,6 +247,36 @@ __global__ void k_divmax(const double* __restrict__ rc, Dims d, const cd* __rest
 }
 
 // Per-block sums over the inner wall of c_n (|u_theta - Re_i delta|^2 + |u_z|^2).
+// Per radial node j (blockIdx.y): block partials of the mode sums
+// sum c_n |u_r|, sum c_n |u_theta|, sum c_n |u_z| over the stored modes
+// (c_0 = 1, c_n = 2), the bounds of max |u_c| over the (theta, z) plane
+// that the CFL estimate of tc_get_diag uses.
+__global__ void k_cflsum(Dims d, const cd* __restrict__ u, double* __restrict__ partial) {
+  __shared__ double red[3][256];
+  const int64_t j = blockIdx.y;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < d.S;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx / d.mt), n = (int)(idx - (int64_t)s * d.mt);
+    if (s == d.nyq) continue;
+    const int64_t o = j * d.S + idx;
+    const cd p = u[o], m = u[d.F + o], z = u[2 * d.F + o];
+    const double c = n == 0 ? 1.0 : 2.0;
+    acc[0] += c * 0.5 * hypot(p.x + m.x, p.y + m.y);  // u_r = (u+ + u-)/2
+    acc[1] += c * 0.5 * hypot(p.x - m.x, p.y - m.y);  // |u_theta| = |u+ - u-|/2
+    acc[2] += c * hypot(z.x, z.y);
+  }
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partial[(j * gridDim.x + blockIdx.x) * 3 + k] = red[k][0];
+}
+
 __global__ void k_slip(Dims d, const cd* __restrict__ u, double* __restrict__ partial) {
   __shared__ double red[256];
   double acc = 0.0;
@@ -621,10 +651,12 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
   const int nb = 1024;
   const int nbd = (int)((d.S + 255) / 256);
   const int np = std::max(nb, nbd);
+  const int nbc = 32;  // blocks per radial node of the CFL sums
+  const size_t ncfl = (size_t)d.n_r * nbc * 3;
   double *dwr = nullptr, *dUc = nullptr, *part = nullptr;
   hipError_t e = hipMalloc(&dwr, d.n_r * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&dUc, d.n_r * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&part, 4 * (size_t)np * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, (4 * (size_t)np + ncfl) * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(dwr, wr.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(dUc, Uc.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) {
@@ -632,9 +664,10 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
     hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->stream, d, c->u, dwr, dUc, 1, part + np);
     hipLaunchKernelGGL(k_divmax, dim3(nbd), dim3(256), 0, c->stream, c->rc_dev, d, c->u, part + 2 * np);
     hipLaunchKernelGGL(k_slip, dim3(nbd), dim3(256), 0, c->stream, d, c->u, part + 3 * np);
+    hipLaunchKernelGGL(k_cflsum, dim3(nbc, d.n_r), dim3(256), 0, c->stream, d, c->u, part + 4 * np);
     e = hipGetLastError();
   }
-  std::vector<double> h(4 * (size_t)np, 0.0);
+  std::vector<double> h(4 * (size_t)np + ncfl, 0.0);
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(dwr);
@@ -649,7 +682,21 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
   out[1] = 0.5 * area * Ep;
   out[2] = dv;
   out[3] = std::sqrt(sl) / std::fabs(d.Re_i == 0.0 ? 1.0 : d.Re_i);
-  out[4] = (double)c->steps;
+  // CFL bound: dt max_j (B_r/dr_j + B_theta/(r_j dtheta) + B_z/dz) on the
+  // physical grid (2 m_theta, m_z), dr_j the distance to the nearer neighbour
+  const double dth = 2.0 * M_PI / (d.kt * 2.0 * d.mt), dz = 2.0 * M_PI / (d.kz * d.mz);
+  double cfl = 0.0;
+  for (int j = 0; j < d.n_r; ++j) {
+    double B[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nbc; ++b)
+      for (int k = 0; k < 3; ++k) B[k] += h[4 * (size_t)np + ((size_t)j * nbc + b) * 3 + k];
+    double dr = HUGE_VAL;
+    if (j > 0) dr = std::min(dr, c->r[j] - c->r[j - 1]);
+    if (j + 1 < d.n_r) dr = std::min(dr, c->r[j + 1] - c->r[j]);
+    cfl = std::max(cfl, B[0] / dr + B[1] / (c->r[j] * dth) + B[2] / dz);
+  }
+  out[4] = d.dt * cfl;
+  out[5] = (double)c->steps;
   return TC_OK;
 }
 

@@ -108,6 +108,32 @@ def test_one_step(name):
     assert rel_l2(to_host(up), u0) == 0.0
 
 
+@pytest.mark.parametrize("name", SIZES)
+def test_diagnostics(name):
+    # tc_get_diag against the oracle's definitions on the workload's state
+    # (sums in a different order: relative agreement to ~1e-13)
+    from oracle import diagnostics as dg
+    S, P, cfg = pair(name)
+    u = tc_inputs.initial_state(P.r, cfg)
+    S.set_state(to_dev(u))
+    d = S.diag()
+    div = np.abs(scheme.div(P, u)[1:-1]).max()
+    ref = dict(energy=dg.energy(P, u), perturbation_energy=dg.perturbation_energy(P, u), max_div=div,
+               slip=dg.wall_slip(P, u), cfl=dg.cfl_bound(P, u))
+    # the divergence of a divergence-free field is a cancellation: bound its
+    # difference by the size of the terms summed, sum |D1_jk| |u_r,k| + |u_r|/r
+    # + a |u+ - u-|/(2r) + |b u_z| at the worst node
+    a, b, r = P.bcast()
+    ur = 0.5 * np.abs(u[0] + u[1])
+    terms = (np.einsum("jk,ksn->jsn", np.abs(P.D1), ur) + ur / r + a * np.abs(u[0] - u[1]) / (2 * r)
+             + np.abs(b * u[2]))
+    tol = dict(max_div=1e-14 * terms[1:-1].max())
+    for k, v in ref.items():
+        print(f"{name} {k}: gpu {d[k]:.15e} oracle {v:.15e}")
+        assert abs(d[k] - v) <= tol.get(k, 1e-12 * abs(v)), k
+    assert d["steps"] == 0
+
+
 def test_trajectory_small():
     S, P, cfg = pair("small")
     u0 = tc_inputs.initial_state(P.r, cfg)

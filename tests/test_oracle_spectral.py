@@ -188,3 +188,47 @@ def test_energy_matches_physical_space_quadrature():
     w[1:] += h / 2
     ref = 0.5 * area * np.sum(w * P.r * ms)
     assert abs(dg.energy(P, u) - ref) <= 1e-13 * ref
+
+
+def _physical_cfl(P, u):
+    """dt max over the nodes and an explicit (P_z, P_theta) grid of
+    |u_r|/dr_j + |u_theta|/(r_j dtheta) + |u_z|/dz, the values synthesised
+    from the coefficients by inverse FFTs."""
+    import scipy.fft as sfft
+    ur, ut, uz = nl.cylindrical(u)
+
+    def phys(f):
+        return sfft.irfft2(nl._pad(P, f), s=(P.p_z, P.p_theta), axes=(-2, -1), norm="forward")
+    h = np.diff(P.r)
+    dr = np.minimum(np.concatenate([h, [np.inf]]), np.concatenate([[np.inf], h]))
+    dth = 2 * np.pi / (P.k_theta * 2 * P.m_theta)
+    dz = 2 * np.pi / (P.k_z * P.m_z)
+    rate = (np.abs(phys(ur)) / dr[:, None, None] + np.abs(phys(ut)) / (P.r * dth)[:, None, None]
+            + np.abs(phys(uz)) / dz)
+    return P.dt * rate.max()
+
+
+def test_cfl_bound_is_an_upper_bound():
+    # the mode-sum bound can only overestimate the physical-grid value, and
+    # for a smooth low-mode state it stays within a small factor of it
+    from oracle import diagnostics as dg
+    cfg = dict(tc_inputs.CONFIGS["small"])
+    P = oracle.Problem(cfg["n_r"], cfg["m_theta"], cfg["m_z"], cfg["eta"], cfg["Re_i"], cfg["Re_o"], cfg["dt"])
+    u = tc_inputs.initial_state(P.r, dict(cfg, amp=0.2))
+    b, c = dg.cfl_bound(P, u), _physical_cfl(P, u)
+    assert c <= b * (1 + 1e-12) and b < 3 * c
+
+
+def test_cfl_bound_exact_for_one_aligned_mode():
+    # Couette flow plus u_theta = 2 A(r) cos(k_z z) (slots l = +-1, n = 0,
+    # A > 0): u_r = u_z = 0 and the largest |u_theta| on every node, at
+    # z = 0, is U + 2A, which is exactly the mode sum
+    from oracle import diagnostics as dg
+    P = oracle.Problem(17, 3, 8, 0.5, 40.0, 0.0, 1e-3, k_theta=2.0, k_z=1.5)
+    u = dg.couette_state(P)
+    A = 3.0 + np.sin(P.r)
+    for s in (1, P.m_z - 1):
+        u[0, :, s, 0] = 1j * A
+        u[1, :, s, 0] = -1j * A
+    b, c = dg.cfl_bound(P, u), _physical_cfl(P, u)
+    assert abs(b - c) <= 1e-13 * c
