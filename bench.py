@@ -253,9 +253,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--stable-dt", type=float, default=None,
+                    help="also time 10 FP64 steps at this dt (default 5e-8 for the production workload, else off; 0: off)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (scale reference for HBM counters)")
     args = ap.parse_args()
+    if args.stable_dt is None:
+        args.stable_dt = 5e-8 if args.workload == "production" else 0.0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -283,6 +287,18 @@ def main():
 
     print("[bench] FP64 step", file=sys.stderr, flush=True)
     f64 = run_gpu(cfg, "fp64", args.steps, args.warmup, u0)
+    stable = None
+    if args.stable_dt > 0:
+        # the same step at a time step inside the scheme's stable range: the
+        # cost does not depend on dt (it only enters 3/(2 dt) in the
+        # factors), and the fields stay finite
+        print(f"[bench] FP64 step at dt={args.stable_dt:g}", file=sys.stderr, flush=True)
+        cs = tc_inputs.Config(cfg)
+        cs["dt"] = args.stable_dt
+        st = run_gpu(cs, "fp64", 10, 2, u0)
+        stable = {"dt": args.stable_dt, "steps": 10, "warmup": 2, "ms_per_step": round(st["seconds"] / 10 * 1e3, 3),
+                  "finite_after_run": st["finite"], "cfl_bound_initial": round(st["cfl0"], 4),
+                  "perturbation_energy_after": st["diag"]["perturbation_energy"]}
     f32 = None
     if not args.no_fp32:
         print("[bench] FP32-bulk step", file=sys.stderr, flush=True)
@@ -310,7 +326,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload_label(cfg, args.workload), "grid_points_per_step": pts},
         "grid_pt_updates_per_s": round(sps * pts, 1),
-        "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3),
+        "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3), "stable_dt_run": stable,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
         "roofline": roof,
