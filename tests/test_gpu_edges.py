@@ -112,3 +112,19 @@ def test_out_of_memory_is_reported_and_recoverable():
     u = tc_inputs.random_state((3, 9, 2, 1), 3)
     assert rel_l2(to_host(S.nonlinear(to_dev(u))), oracle.nonlinear_rot(P, u)) < 1e-12
     S.close()
+
+
+def test_default_dealiased_grid_rounds_up():
+    # p_theta = p_z = 0 picks the smallest supported lengths that meet the
+    # 3/2 rule: m_theta = 24 needs 70 -> 96, m_z = 40 needs 58 -> 64; the
+    # result must equal the oracle's on that grid (any grid meeting the rule
+    # gives the same truncated product, up to rounding)
+    from paper_1311_2481_amd import Solver
+    args = (12, 24, 40, 0.6, 70.0, -10.0, 1e-3)
+    S = Solver(*args)
+    P = oracle.Problem(*args, p_theta=96, p_z=64)
+    u = tc_inputs.random_state((3, 12, 40, 24), 5)
+    err = rel_l2(to_host(S.nonlinear(to_dev(u))), oracle.nonlinear_rot(P, u))
+    print(f"default grid: nonlinear rel_l2 {err:.2e}")
+    assert err < 1e-12
+    S.close()
