@@ -110,8 +110,7 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
 // precisions): it removes their bank conflicts.  Persistent prefetching z
 // workgroups (TC_Z_PREFETCH) are kept as an option for float data; one tile
 // per workgroup measured as fast and uses far fewer VGPRs.
-// Tile width: up to TC_Z_WG threads (twice that for the wide FP64 shape
-// below) and TC_Z_LDS_CAP bytes of LDS per workgroup, which at 1536 points
+// Tile width: up to TC_Z_WG threads (twice that for the wide shape below) and TC_Z_LDS_CAP bytes of LDS per workgroup, which at 1536 points
 // gives 4 FP64 (8 float) columns, 64 bytes of every row.  Narrower tiles (2 FP64 columns, 32 bytes per row, three
 // workgroups per CU) wrote about 1.4x their bytes to HBM and ran at a speed
 // that depended on where the buffers' pages landed (k_zinv 16.6-22.9 ms on
@@ -131,11 +130,11 @@ hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
 #endif
 template <typename T, int L> struct ZShape {
   static constexpr bool SWZ = (TC_Z_SWIZZLE == 2 || (TC_Z_SWIZZLE == 1 && sizeof(T) == 8)) && L % 16 == 0;
-  // FP64 at 1536 points and above: 256 threads per column (6-8 values
-  // each), 16 waves in the one workgroup a CU holds, measured 7% faster
-  // than 128; shorter transforms would leave most of 256 threads idle
-  static constexpr bool WIDE = sizeof(T) == 8 && L >= 1536;
-  static constexpr int TPF = WIDE ? 256 : L >= 512 ? (sizeof(T) == 8 ? 128 : 64) : (L >= 128 ? 32 : 8);
+  // 1536 points and above: 256 (FP64) or 128 (float) threads per column,
+  // 16 waves in the one workgroup a CU holds; measured 5-10% faster than
+  // half as many.  Shorter transforms would leave many of them idle.
+  static constexpr bool WIDE = L >= 1536;
+  static constexpr int TPF = WIDE ? (sizeof(T) == 8 ? 256 : 128) : L >= 512 ? (sizeof(T) == 8 ? 128 : 64) : (L >= 128 ? 32 : 8);
   static constexpr int LDS_CAP = TC_Z_LDS_CAP;
   static constexpr int NF0 = (WIDE ? 2 * TC_Z_WG : TC_Z_WG) / TPF;
   static constexpr int NF1 = LDS_CAP / (lds_len<L, SWZ>() * (int)sizeof(C2<T>));
