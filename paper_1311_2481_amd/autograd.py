@@ -70,4 +70,4 @@ def final_energy_and_gradient(solver, u_base, u0_pert, nsteps, every=20):
     x = u0_pert.detach().clone().requires_grad_(True)
     J = TCSteps.apply(x, solver, u_base, nsteps, every)
     J.backward()
-    return float(J), x.grad
+    return float(J.detach()), x.grad

@@ -55,16 +55,21 @@ __host__ __device__ inline int64_t slot_tiles(const Dims& d) {
   return (d.S + SLOT_BLOCK - 1) / SLOT_BLOCK * (int64_t)d.n_r;
 }
 
+// 32-bit index arithmetic: the tile count (at most ceil(S / 256) * 4096) and
+// the slot count S of any grid tc_init accepts are far below 2^31, and a
+// 64-bit division costs several times a 32-bit one.
 __device__ __forceinline__ bool make_slot(const Dims& d, Slot& q) {
-  const int64_t ntiles = slot_tiles(d);
-  const int64_t per = (ntiles + 7) / 8;
-  const int64_t id = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const unsigned ntiles = (unsigned)slot_tiles(d);
+  const unsigned per = (ntiles + 7u) / 8u;
+  const unsigned id = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
   if (id >= ntiles) return false;
-  q.k = (int)(id % d.n_r);
-  q.idx = (id / d.n_r) * SLOT_BLOCK + threadIdx.x;
+  const unsigned nr = (unsigned)d.n_r, mt = (unsigned)d.mt;
+  q.k = (int)(id % nr);
+  const unsigned idx = (id / nr) * SLOT_BLOCK + threadIdx.x;
+  q.idx = idx;
   if (q.idx >= d.S) return false;
-  q.s = (int)(q.idx / d.mt);
-  q.n = (int)(q.idx - (int64_t)q.s * d.mt);
+  q.s = (int)(idx / mt);
+  q.n = (int)(idx - (unsigned)q.s * mt);
   q.a = q.n * d.kt;
   q.b = (q.s < d.half ? q.s : q.s - d.mz) * d.kz;
   q.nyq = q.s == d.nyq;
