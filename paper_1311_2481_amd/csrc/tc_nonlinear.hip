@@ -89,13 +89,68 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dim
   }
 }
 
+// The same curl with one thread per (radial node, slot) point (grid: x over
+// slots, y over nodes): each thread applies row k of D1 to the 9 rows
+// around it.  For small grids, where the marching kernel has too few lanes
+// to hide memory latency; the rows it re-reads are then cache resident.
+__global__ __launch_bounds__(256) void k_curl_points(const double* __restrict__ rc, Dims d, const cd* __restrict__ u,
+                                                     cd* __restrict__ w) {
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)d.S) return;
+  const int k = blockIdx.y;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const int64_t o = k * S + idx;
+  const int s = (int)(idx / (unsigned)d.mt), n = (int)(idx - (unsigned)s * (unsigned)d.mt);
+  if (s == d.nyq) {
+    w[o] = cd{0, 0};
+    w[F + o] = cd{0, 0};
+    w[2 * F + o] = cd{0, 0};
+    return;
+  }
+  const double a = n * d.kt;
+  const double b = (s < d.half ? s : s - d.mz) * d.kz;
+  const double* R = rc + (int64_t)k * RC_N;
+  const double ir = R[RC_IR];
+  cd dp = {0, 0}, dmn = {0, 0}, dz = {0, 0};
+#pragma unroll
+  for (int t = 0; t < NB9; ++t) {
+    const int i = k - HW + t;
+    if (i < 0 || i > M) continue;
+    const double c = R[RC_W1 + t];
+    const int64_t oi = i * S + idx;
+    const cd p = u[oi], m = u[F + oi], z = u[2 * F + oi];
+    dp.x = fma(c, p.x, dp.x); dp.y = fma(c, p.y, dp.y);
+    dmn.x = fma(c, m.x, dmn.x); dmn.y = fma(c, m.y, dmn.y);
+    dz.x = fma(c, z.x, dz.x); dz.y = fma(c, z.y, dz.y);
+  }
+  const cd up = u[o], um = u[F + o], uz = u[2 * F + o];
+  // omega+ = i (a/r uz - D1 uz) - b u+ ;  omega- = i (a/r uz + D1 uz) + b u-
+  const cd tp = {a * ir * uz.x - dz.x, a * ir * uz.y - dz.y};
+  const cd tm = {a * ir * uz.x + dz.x, a * ir * uz.y + dz.y};
+  const cd op = {-tp.y - b * up.x, tp.x - b * up.y};
+  const cd om = {-tm.y + b * um.x, tm.x + b * um.y};
+  // omega_z = -(i/2) [ (D1 + (1+a)/r) u+ - (D1 + (1-a)/r) u- ]
+  const cd q = {dp.x + (1.0 + a) * ir * up.x - dmn.x - (1.0 - a) * ir * um.x,
+                dp.y + (1.0 + a) * ir * up.y - dmn.y - (1.0 - a) * ir * um.y};
+  w[o] = op;
+  w[F + o] = om;
+  w[2 * F + o] = cd{0.5 * q.y, -0.5 * q.x};
+}
+
 __global__ void k_clear_words(unsigned int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
   const int64_t blocks = (c->d.S + 255) / 256;
-  hipLaunchKernelGGL(k_curl, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, omega);
+  // marching lanes (one per slot) fill fewer than 2 waves per SIMD below
+  // 131072 slots per plane: use one thread per point instead
+  if (c->d.S < 131072)
+    hipLaunchKernelGGL(k_curl_points, dim3((unsigned)blocks, (unsigned)c->d.n_r), dim3(256), 0, c->stream, c->rc_dev,
+                       c->d, u, omega);
+  else
+    hipLaunchKernelGGL(k_curl, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, omega);
   return hipGetLastError();
 }
 
