@@ -331,6 +331,7 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, ru, out_u, out_up, nin, out_np, ntot);
   TC_TRY(hipGetLastError());
   // nonlinear term, transposed: forward fields u, omega(u) and the cotangent N_tot
+  c->omega_fresh = false;  // the context's curl buffer now holds curl(fwd u)
   TC_TRY(launch_curl(c, u, c->omega));
   ZIo zi{};
   for (int k = 0; k < 3; ++k) {

@@ -90,6 +90,7 @@ struct tc_ctx {
   tc::cd* N_cur = nullptr;   // N^i     (3 fields)
   tc::cd* p = nullptr;       // pressure (1 field)
   tc::cd* omega = nullptr;   // curl work (3 fields)
+  bool omega_fresh = false;  // omega holds curl(u) of the current state
   tc::cd* aux = nullptr;     // adjoint work (allocated on first use)
   size_t aux_bytes = 0;
   void* inter = nullptr;     // nonlinear intermediate, batch planes
@@ -115,8 +116,11 @@ hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x)
 // transposed solves of nop (1, or 3 starting at OP_HP) operators on
 // consecutive fields rhs + k F -> x + k F (x may alias rhs)
 hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x);
+// omega_out (nullable): where the last sweep also writes curl(u_next) on
+// grids where pc_fuses_curl() holds (ignored elsewhere)
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev_scratch,
-                     cd* u_next, cd* p, int want_p);
+                     cd* u_next, cd* p, int want_p, cd* omega_out);
+bool pc_fuses_curl(const tc_ctx* c);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

@@ -226,10 +226,13 @@ __device__ __forceinline__ bool make_lane1(const Dims& d, Lane1& L) {
 
 #define TC_PC_ARGS                                                                                              \
   const double *__restrict__ rc, const double *__restrict__ fac, Dims d, const cd *__restrict__ u, const cd *up, \
-      const cd *__restrict__ N, cd *Np, cd *un, cd *p, int want_p
+      const cd *__restrict__ N, cd *Np, cd *un, cd *p, int want_p, cd *omg
 
 #ifndef PC_CH
 #define PC_CH 4
+#endif
+#ifndef TC_FUSE_CURL
+#define TC_FUSE_CURL 1
 #endif
 // Each sweep runs in three phases (rows that only enter the lagging
 // stencil window, rows that do both parts, rows that only leave it), so the
@@ -647,6 +650,53 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     for (int c = 1; c <= 4; ++c) y = cnfma(y, fu[c], fw[c]);
     fw[0] = cmuls(y, fu[0]);
   };
+  // Fused curl of the new velocity (large grids, omg != NULL): the rows of
+  // u^{i+1} enter a 9-row window as they are finished (descending), and
+  // omega = curl u^{i+1} of row c is formed once rows c-4..c+4 are known,
+  // with the arithmetic of the standalone curl kernel; the next step's
+  // nonlinear term then needs no separate curl pass over u.
+  cd uw[TC_FUSE_CURL && CH == 1 ? NB9 : 1][3];
+  if constexpr (TC_FUSE_CURL && CH == 1)
+    for (int k = 0; k < NB9; ++k) uw[k][0] = uw[k][1] = uw[k][2] = cz();
+  auto curl_push = [&](int i, const cd (&v)[3]) {
+    if constexpr (TC_FUSE_CURL && CH == 1) {
+      for (int k = NB9 - 1; k >= 1; --k) {
+        uw[k][0] = uw[k - 1][0]; uw[k][1] = uw[k - 1][1]; uw[k][2] = uw[k - 1][2];
+      }
+      uw[0][0] = v[0]; uw[0][1] = v[1]; uw[0][2] = v[2];
+      const int c = i + HW;  // uw[k] holds row c - HW + k
+      if (c > M) return;
+      const double* R = rc + (int64_t)c * RC_N;
+      const double ir = R[RC_IR];
+      cd dp = cz(), dmn = cz(), dz = cz();
+#pragma unroll
+      for (int k = 0; k < NB9; ++k) {
+        const double w = R[RC_W1 + k];
+        dp.x = fma(w, uw[k][0].x, dp.x); dp.y = fma(w, uw[k][0].y, dp.y);
+        dmn.x = fma(w, uw[k][1].x, dmn.x); dmn.y = fma(w, uw[k][1].y, dmn.y);
+        dz.x = fma(w, uw[k][2].x, dz.x); dz.y = fma(w, uw[k][2].y, dz.y);
+      }
+      const cd upv = uw[HW][0], umv = uw[HW][1], uzv = uw[HW][2];
+      const double b = L.b;
+      // omega+ = i (a/r uz - D1 uz) - b u+ ;  omega- = i (a/r uz + D1 uz) + b u-
+      const cd tp = {a * ir * uzv.x - dz.x, a * ir * uzv.y - dz.y};
+      const cd tm = {a * ir * uzv.x + dz.x, a * ir * uzv.y + dz.y};
+      const cd op = {-tp.y - b * upv.x, tp.x - b * upv.y};
+      const cd om = {-tm.y + b * umv.x, tm.x + b * umv.y};
+      // omega_z = -(i/2) [ (D1 + (1+a)/r) u+ - (D1 + (1-a)/r) u- ]
+      const cd q = {dp.x + (1.0 + a) * ir * upv.x - dmn.x - (1.0 - a) * ir * umv.x,
+                    dp.y + (1.0 + a) * ir * upv.y - dmn.y - (1.0 - a) * ir * umv.y};
+      const int64_t o = c * S + L.o;
+      omg[o] = op;
+      omg[F + o] = om;
+      omg[2 * F + o] = cd{0.5 * q.y, -0.5 * q.x};
+      if (nyq_lane) {
+        const int64_t on = c * S + (int64_t)d.nyq * d.mt + (L.dm % d.mt);
+        omg[on] = cz(); omg[F + on] = cz(); omg[2 * F + on] = cz();
+      }
+    }
+  };
+  const bool fuse = TC_FUSE_CURL && CH == 1 && omg != nullptr;
   // correction and pressure update at row i
   auto correct = [&](int i, const cd (&us)[3], cd pv) {
     const double* R = rc + (int64_t)i * RC_N;
@@ -656,9 +706,12 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k]);
     const cd ph = fw[HW];
     const int64_t o = i * S + L.o;
-    un[o] = csub(us[0], cnfma(d1, a * ir, ph));
-    un[F + o] = csub(us[1], cfma(d1, a * ir, ph));
-    un[2 * F + o] = csub(us[2], cimul(ph, L.b));
+    const cd v[3] = {csub(us[0], cnfma(d1, a * ir, ph)), csub(us[1], cfma(d1, a * ir, ph)),
+                     csub(us[2], cimul(ph, L.b))};
+    un[o] = v[0];
+    un[F + o] = v[1];
+    un[2 * F + o] = v[2];
+    if (fuse) curl_push(i, v);
     if (want_p) p[o] = cfma(pv, c_p, ph);
     if (nyq_lane) {
       const int64_t on = i * S + (int64_t)d.nyq * d.mt + (L.dm % d.mt);
@@ -719,6 +772,11 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     shift();
     fw[0] = cz();
     correct(jj + HW, us, pv);
+  }
+  if (fuse) {
+    // the last HW rows of omega: rows below the inner wall count as zero
+    const cd zero3[3] = {cz(), cz(), cz()};
+    for (int i = -1; i >= -HW; --i) curl_push(i, zero3);
   }
 }
 
@@ -837,20 +895,25 @@ hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
   return hipGetLastError();
 }
 
+// Few waves (fewer than 2 per SIMD): too few to hide memory latency, so
+// each lane loads PC_CH rows before working through them; otherwise one
+// row at a time, which keeps the register count (and the occupancy that
+// saturates HBM on large grids) down.
+static bool pc_chunked(const tc_ctx* c) { return (c->d.ndm + 31) / 32 < 2 * 4 * 256; }
+
+bool pc_fuses_curl(const tc_ctx* c) { return TC_FUSE_CURL && !pc_chunked(c); }
+
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
-                     int want_p) {
+                     int want_p, cd* omega_out) {
   const int blocks = (c->d.ndm + 31) / 32;
-  // Few waves (fewer than 2 per SIMD): too few to hide memory latency, so
-  // each lane loads PC_CH rows before working through them; otherwise one
-  // row at a time, which keeps the register count (and the occupancy that
-  // saturates HBM on large grids) down.
-  const bool chunked = blocks < 2 * 4 * 256;
+  const bool chunked = pc_chunked(c);
+  cd* omg = pc_fuses_curl(c) ? omega_out : nullptr;
   using K = void (*)(TC_PC_ARGS);
   const K ks[2][4] = {{k_pc1<1>, k_pc2<1>, k_pc3<1>, k_pc4<1>},
                       {k_pc1<PC_CH>, k_pc2<PC_CH>, k_pc3<PC_CH>, k_pc4<PC_CH>}};
   for (const K k : ks[chunked ? 1 : 0]) {
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, u, u_prev, N, N_prev,
-                       u_next, p, want_p);
+                       u_next, p, want_p, omg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -128,3 +128,34 @@ def test_default_dealiased_grid_rounds_up():
     print(f"default grid: nonlinear rel_l2 {err:.2e}")
     assert err < 1e-12
     S.close()
+
+
+def test_fused_curl_matches_standalone():
+    # On large grids (at least 2048 waves of predictor-corrector lanes) the
+    # last sweep of a step also forms the curl of the new velocity, and the
+    # next step skips its curl kernel.  Two steps in one call (the second
+    # using that curl) must equal one step, a reload of the state (which
+    # discards it) and one more step (which computes the curl on its own).
+    from paper_1311_2481_amd import Solver
+    n_r, m_theta, m_z = 16, 128, 1040      # 128 * 520 distinct modes -> 2080 waves
+    args = (n_r, m_theta, m_z, 0.6, 300.0, -50.0, 1e-4)
+    cfg = tc_inputs.Config(n_r=n_r, m_theta=m_theta, m_z=m_z, eta=0.6, Re_i=300.0, Re_o=-50.0, dt=1e-4,
+                           amp=0.05, envelope="k53", seed=9, k_theta=1.0, k_z=1.0, alpha=0.0)
+    A = Solver(*args)
+    u0 = to_dev(tc_inputs.initial_state(A.radial_nodes(), cfg))
+    A.set_state(u0)
+    A.step(2)
+    ua, pa = A.get_state()
+    B = Solver(*args)
+    B.set_state(u0)
+    B.step(1)
+    u1 = B.get_state(with_pressure=False)
+    up1, Np1 = B.get_history()
+    B.set_state(u1, up1, Np1)
+    B.step(1)
+    ub, pb = B.get_state()
+    eu, ep = rel_l2(to_host(ua), to_host(ub)), rel_l2(to_host(pa), to_host(pb))
+    print(f"fused vs standalone curl after two steps: u {eu:.2e}, p {ep:.2e}")
+    assert eu < 1e-14 and ep < 1e-13
+    A.close()
+    B.close()
