@@ -1,4 +1,5 @@
-"""Diagnostics of a spectral state (energies, divergence, wall slip).
+"""Diagnostics of a spectral state (energies, divergence, wall slip, CFL
+bound, wall torque).
 
 Volume integrals use trapezoid weights on the radial nodes and Parseval in
 (theta, z): a real field's mean square over a (theta, z) plane is
@@ -100,3 +101,30 @@ def cfl_bound(prob, u):
     dz = 2.0 * np.pi / (prob.k_z * prob.m_z)
     rate = plane_bound(ur) / dr + plane_bound(ut) / (r * dth) + plane_bound(uz) / dz
     return prob.dt * float(np.max(rate))
+
+
+def quasi_nusselt(prob, u):
+    """Quasi-Nusselt number at the inner and outer cylinder (Sec. 5.4): the
+    torque the fluid exerts on a cylinder divided by that of circular
+    Couette flow at the same Reynolds numbers.
+
+    On a cylinder the viscous torque is proportional to r^3 d<omega>/dr,
+    with <omega> = <u_theta> / r the angular velocity averaged over theta and
+    z, i.e. the (l, n) = (0, 0) coefficient of u_theta divided by r (u_r
+    vanishes at the walls, so the convective part of the angular-velocity
+    flux does not enter there).  For Couette flow <omega> = C1 + C2 / r^2
+    and r^3 d<omega>/dr = -2 C2 on every radius, hence
+
+        Nu_w = r^3 (D1 <omega>)(r) / (-2 C2)   at r = r_i and r = r_o,
+
+    with D1 the finite-difference first derivative (its wall rows).
+    Returns (Nu_inner, Nu_outer); NaN when C2 = 0 (no laminar torque).
+    """
+    eta, Re_i, Re_o = prob.eta, prob.Re_i, prob.Re_o
+    C2 = eta * (Re_i - eta * Re_o) / ((1.0 - eta) * (1.0 - eta ** 2))
+    if C2 == 0.0:
+        return float("nan"), float("nan")
+    ut_mean = (-0.5j * (u[0, :, 0, 0] - u[1, :, 0, 0])).real
+    dw = prob.D1 @ (ut_mean / prob.r)
+    r = prob.r
+    return (float(r[0] ** 3 * dw[0] / (-2.0 * C2)), float(r[-1] ** 3 * dw[-1] / (-2.0 * C2)))

@@ -232,3 +232,42 @@ def test_cfl_bound_exact_for_one_aligned_mode():
         u[1, :, s, 0] = -1j * A
     b, c = dg.cfl_bound(P, u), _physical_cfl(P, u)
     assert abs(b - c) <= 1e-13 * c
+
+
+def test_quasi_nusselt_of_couette_flow_tends_to_one():
+    # circular Couette flow is the laminar reference, so both cylinders give
+    # Nu = 1 up to the error of the 5-point wall rows of D1, which is
+    # O(h^4) in the wall spacing h
+    from oracle import diagnostics as dg
+    errs, hs = [], []
+    for n_r in (17, 33, 65):
+        P = oracle.Problem(n_r, 2, 4, 0.5, 100.0, -30.0, 1e-3)
+        nu = dg.quasi_nusselt(P, dg.couette_state(P))
+        errs.append(max(abs(nu[0] - 1.0), abs(nu[1] - 1.0)))
+        hs.append(P.r[1] - P.r[0])
+    orders = [np.log(errs[k] / errs[k + 1]) / np.log(hs[k] / hs[k + 1]) for k in range(2)]
+    assert errs[-1] < 1e-9 and min(orders) > 3.5
+
+
+def test_quasi_nusselt_exact_for_quartic_angular_velocity():
+    # <u_theta> = r q(r) with q quartic: the wall rows of D1 (5 points) are
+    # exact on it, so Nu at each wall is -r^3 q'(r) / (2 C2) to rounding.
+    # A radial mean flow and every other mode must not enter.
+    from oracle import diagnostics as dg
+    P = oracle.Problem(21, 3, 6, 0.6, 80.0, 25.0, 1e-3)
+    c = np.array([0.7, -1.3, 0.4, 2.1, -0.9])             # q(x) = sum c_k x^k, x = r - r_i
+    x = P.r - P.r[0]
+    q = np.polyval(c[::-1], x)
+    dq = np.polyval((c[1:] * np.arange(1, 5))[::-1], x)
+    u = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), 19)
+    ur = np.cos(P.r)                                       # a radial (0, 0) component
+    u[0, :, 0, 0] = ur + 1j * P.r * q
+    u[1, :, 0, 0] = ur - 1j * P.r * q
+    C2 = P.eta * (P.Re_i - P.eta * P.Re_o) / ((1 - P.eta) * (1 - P.eta ** 2))
+    want = -P.r ** 3 * dq / (2 * C2)
+    got = dg.quasi_nusselt(P, u)
+    assert abs(got[0] - want[0]) <= 1e-11 * abs(want[0])
+    assert abs(got[1] - want[-1]) <= 1e-11 * abs(want[-1])
+    # no laminar torque (C2 = 0 on Re_i = eta Re_o): undefined
+    Q = oracle.Problem(9, 1, 2, 0.5, 10.0, 20.0, 1e-3)
+    assert all(np.isnan(dg.quasi_nusselt(Q, dg.couette_state(Q))))
