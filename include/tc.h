@@ -157,15 +157,18 @@ tc_status tc_step_adjoint(tc_ctx* ctx, const void* fwd, const void* adj_in, void
  * seed of the reverse sweep for the final-energy objective. */
 tc_status tc_perturbation_energy_gradient(tc_ctx* ctx, const void* u, void* g);
 
-/* Diagnostics of the current state into HOST memory (6 doubles):
+/* Diagnostics of the current state into HOST memory (8 doubles):
  * kinetic energy, perturbation energy (against circular Couette flow),
  * max |div u| over interior nodes, relative tangential wall slip at r_i
  * (Sec. 5.3), an upper bound of the advective CFL number
  * dt max (|u_r|/dr + |u_theta|/(r dtheta) + |u_z|/dz) over the radial nodes
  * (per node the plane maximum of each component bounded by sum c_n |u_ln|;
  * dr the distance to the nearer neighbouring node, dtheta and dz the
- * spacings of the (2 m_theta, m_z) physical grid), and the number of steps
- * taken.  Synchronous. */
+ * spacings of the (2 m_theta, m_z) physical grid), the number of steps
+ * taken, and the quasi-Nusselt numbers Nu_omega at r_i and at r_o (Sec. 5.4:
+ * the torque on that cylinder, r^3 d<u_theta/r>/dr from the theta-z mean
+ * by the wall row of D1, over its value -2 C2 in circular Couette flow;
+ * NaN when C2 = 0).  Synchronous. */
 tc_status tc_get_diag(tc_ctx* ctx, double* out_host);
 
 /* Check the current velocity for non-finite values: TC_ENONFINITE if any.

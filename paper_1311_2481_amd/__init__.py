@@ -178,10 +178,10 @@ class Solver:
         return g
 
     def diag(self):
-        out = np.zeros(6)
+        out = np.zeros(8)
         self._check(self.lib.tc_get_diag(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return dict(energy=out[0], perturbation_energy=out[1], max_div=out[2], slip=out[3], cfl=out[4],
-                    steps=int(out[5]))
+                    steps=int(out[5]), nu_inner=out[6], nu_outer=out[7])
 
     def check_finite(self):
         st = self.lib.tc_check_finite(self.ctx)

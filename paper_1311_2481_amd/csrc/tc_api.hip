@@ -282,6 +282,15 @@ __global__ void k_cflsum(Dims d, const cd* __restrict__ u, double* __restrict__ 
     for (int k = 0; k < 3; ++k) partial[(j * gridDim.x + blockIdx.x) * 3 + k] = red[k][0];
 }
 
+// theta-z mean of u_theta on every node: the real part of the (l, n) = (0, 0)
+// coefficient, Re(-i (u+ - u-) / 2) = Im(u+ - u-) / 2.
+__global__ void k_mean_utheta(Dims d, const cd* __restrict__ u, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.n_r) return;
+  const int64_t o = (int64_t)j * d.S;
+  out[j] = 0.5 * (u[o].y - u[d.F + o].y);
+}
+
 __global__ void k_slip(Dims d, const cd* __restrict__ u, double* __restrict__ partial) {
   __shared__ double red[256];
   double acc = 0.0;
@@ -660,10 +669,13 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
   const int np = std::max(nb, nbd);
   const int nbc = 32;  // blocks per radial node of the CFL sums
   const size_t ncfl = (size_t)d.n_r * nbc * 3;
+  // after the partial sums: the theta-z mean of u_theta on every node, for
+  // the wall torques
+  const size_t o00 = 4 * (size_t)np + ncfl, n00 = (size_t)d.n_r;
   double *dwr = nullptr, *dUc = nullptr, *part = nullptr;
   hipError_t e = hipMalloc(&dwr, d.n_r * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&dUc, d.n_r * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&part, (4 * (size_t)np + ncfl) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, (o00 + n00) * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(dwr, wr.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(dUc, Uc.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) {
@@ -672,9 +684,10 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
     hipLaunchKernelGGL(k_divmax, dim3(nbd), dim3(256), 0, c->stream, c->rc_dev, d, c->u, part + 2 * np);
     hipLaunchKernelGGL(k_slip, dim3(nbd), dim3(256), 0, c->stream, d, c->u, part + 3 * np);
     hipLaunchKernelGGL(k_cflsum, dim3(nbc, d.n_r), dim3(256), 0, c->stream, d, c->u, part + 4 * np);
+    hipLaunchKernelGGL(k_mean_utheta, dim3((d.n_r + 255) / 256), dim3(256), 0, c->stream, d, c->u, part + o00);
     e = hipGetLastError();
   }
-  std::vector<double> h(4 * (size_t)np + ncfl, 0.0);
+  std::vector<double> h(o00 + n00, 0.0);
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(dwr);
@@ -704,6 +717,21 @@ tc_status tc_get_diag(tc_ctx* c, double* out) {
   }
   out[4] = d.dt * cfl;
   out[5] = (double)c->steps;
+  // Quasi-Nusselt numbers: r^3 d<omega>/dr at each wall over its Couette
+  // value -2 C2, <omega> = <u_theta>/r, d/dr by the wall rows of D1
+  const int M = d.n_r - 1;
+  if (C2 == 0.0) {
+    out[6] = out[7] = std::nan("");
+  } else {
+    auto omega = [&](int k) { return h[o00 + k] / c->r[k]; };
+    for (int w = 0; w < 2; ++w) {
+      const int j = w ? M : 0;
+      const int lo = std::max(0, j - HW), hi = std::min(M, j + HW);
+      double dw = 0.0;
+      for (int k = lo; k <= hi; ++k) dw += c->rc[(size_t)j * RC_N + RC_W1 + (k - j + HW)] * omega(k);
+      out[6 + w] = c->r[j] * c->r[j] * c->r[j] * dw / (-2.0 * C2);
+    }
+  }
   return TC_OK;
 }
 

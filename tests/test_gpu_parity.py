@@ -128,10 +128,36 @@ def test_diagnostics(name):
     terms = (np.einsum("jk,ksn->jsn", np.abs(P.D1), ur) + ur / r + a * np.abs(u[0] - u[1]) / (2 * r)
              + np.abs(b * u[2]))
     tol = dict(max_div=1e-14 * terms[1:-1].max())
+    ref.update(nu_tol(P, u, tol))
     for k, v in ref.items():
         print(f"{name} {k}: gpu {d[k]:.15e} oracle {v:.15e}")
         assert abs(d[k] - v) <= tol.get(k, 1e-12 * abs(v)), k
     assert d["steps"] == 0
+    # a mean flow sheared away from Couette's at both walls (Nu != 1)
+    x = (P.r - P.r[0]) / (P.r[-1] - P.r[0])
+    bump = 0.3 * abs(P.Re_i) * x * (1 - x) * np.cos(3 * x)
+    u[0, :, 0, 0] += 1j * bump
+    u[1, :, 0, 0] -= 1j * bump
+    S.set_state(to_dev(u))
+    d, tol = S.diag(), {}
+    for k, v in nu_tol(P, u, tol).items():
+        print(f"{name} sheared mean {k}: gpu {d[k]:.15e} oracle {v:.15e}")
+        assert abs(v - 1) > 0.1 and abs(d[k] - v) <= tol[k], k
+
+
+def nu_tol(P, u, tol):
+    """Oracle wall torques of u, with their tolerances put into tol: the D1
+    wall row sums terms far larger than the result (weights ~ 1 / h_wall),
+    and the two sides' weights differ by rounding."""
+    from oracle import diagnostics as dg
+    nu = dg.quasi_nusselt(P, u)
+    C2 = P.eta * (P.Re_i - P.eta * P.Re_o) / ((1 - P.eta) * (1 - P.eta ** 2))
+    om = np.abs((-0.5j * (u[0, :, 0, 0] - u[1, :, 0, 0])).real / P.r)
+    out = {}
+    for key, j, v in (("nu_inner", 0, nu[0]), ("nu_outer", -1, nu[1])):
+        out[key] = v
+        tol[key] = 1e-14 * abs(P.r[j]) ** 3 * (np.abs(P.D1[j]) @ om) / abs(2 * C2) + 1e-13 * abs(v)
+    return out
 
 
 def test_trajectory_small():

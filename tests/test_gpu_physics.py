@@ -1,6 +1,7 @@
 """Physics checks of the whole GPU path against what the paper reports:
 the onset of wavy vortex flow and the wave speed of wavy vortices (Sec. 5.2),
-and the order in dt of the wall slip (Sec. 5.3).
+the order in dt of the wall slip (Sec. 5.3), and the balance of the wall
+torques (quasi-Nusselt numbers, Sec. 5.4) in a steady pattern.
 
 Onset
 -----
@@ -174,20 +175,25 @@ def wave_speed(n_r, dt=2e-5, settle=60000, tau=500, apart=5000):
         omega = -math.atan2(z.imag, z.real) / (W["k_theta"] * tau * dt)
         out.append(omega * r_i / W["Re_i"])
     ratio = abs(z) / float((a.abs() ** 2).sum())
-    slip = S.diag()["slip"]
+    diag = S.diag()
     assert S.check_finite()
     S.close()
-    return out[0], out[1], ratio, slip
+    return out[0], out[1], ratio, diag
 
 
 @pytest.mark.parametrize("n_r,tol", [(32, 3e-5), (64, 1e-5)])
 def test_wavy_vortex_wave_speed_matches_paper(n_r, tol):
-    c1, c2, ratio, slip = wave_speed(n_r)
+    c1, c2, ratio, diag = wave_speed(n_r)
+    nu_i, nu_o = diag["nu_inner"], diag["nu_outer"]
     print(f"n_r = {n_r}: c = {c1:.7f}, {c2:.7f} (paper {C_PAPER}); |correlation| / energy {ratio:.8f}; "
-          f"relative slip {slip:.2e}")
+          f"relative slip {diag['slip']:.2e}; Nu_omega inner {nu_i:.8f}, outer {nu_o:.8f}")
     # a rigidly rotating pattern: the speed is steady and the n = 1 shape
     # only turns
     assert abs(c1 - c2) < 1e-6 and abs(ratio - 1) < 1e-6
+    # its theta-z mean is then steady, so the angular-velocity flux is the
+    # same through every cylinder: equal torques on both walls (up to the
+    # radial discretisation), above the laminar one (Sec. 5.4)
+    assert nu_i > 1.05 and abs(nu_i - nu_o) < 1e-4 * nu_i
     # the phase advance per window (k_theta omega tau dt ~ 1.4 rad) is below
     # pi, so the measured speed is not aliased
     assert abs(c2 - C_PAPER) < tol
