@@ -1,13 +1,19 @@
 """Parity at the production size (N_r = 512, 1536 x 1536 dealiased planes),
 sampled where the oracle cannot afford the whole field: the nonlinear term
-on 8 radial planes (each depends on its plane and 4 neighbours) and every
-solve kind on 256 distinct modes (each independent)."""
+on 8 radial planes (each depends on its plane and 4 neighbours), every
+solve kind on 256 distinct modes (each independent), and two whole steps in
+the benchmark's launch configuration, checked on sampled modes (the
+predictor-corrector) and planes (the nonlinear term of the second step,
+built from the curl that the first step's last sweep forms)."""
+import copy
+
 import numpy as np
 import pytest
 
 import oracle
 import tc_inputs
 from oracle import nonlinear as nl
+from oracle import scheme
 
 pytestmark = pytest.mark.gpu
 
@@ -92,4 +98,124 @@ def test_production_solve_sampled_modes(kind):
     # near-wall spacing ~1e-5): two LU solvers differ at ~1e-10 there
     assert err < (1e-8 if kind == "P" else 1e-12)
     del rhs, x
+    torch.cuda.empty_cache()
+
+
+def _node_jittered(P, seed):
+    """Copy of P on nodes moved by independent one-ulp perturbations (walls
+    fixed), with D1 and D2 rebuilt: a rounding floor for whole steps."""
+    from oracle.radial import fd_matrices
+    Q = copy.copy(P)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = P.r.copy()
+    r[1:-1] *= 1.0 + 1.1e-16 * rng.choice([-1.0, 1.0], size=P.n_r - 2)
+    Q.r = r
+    Q.D1, Q.D2 = fd_matrices(r)
+    Q._lu = {}
+    return Q
+
+
+def _mode_problem(T, labs, n, k_theta, k_z):
+    """Problem holding one production mode (|l|, n): the predictor-corrector
+    couples no modes and sees (l, n) only through a = n k_theta and
+    b = l k_z, so T's grid (m_theta = 2, m_z = 4) with k_theta' = n k_theta
+    and k_z' = |l| k_z reproduces that mode in its slot (+-1, 1) (slot 0 or
+    column 0 when |l| or n is 0).  Returns (problem, n', slots')."""
+    Q = copy.copy(T)
+    Q.k_theta = n * k_theta if n else k_theta
+    Q.k_z = labs * k_z if labs else k_z
+    Q.a, Q.b, Q._lu = Q.n * Q.k_theta, Q.l * Q.k_z, {}
+    return Q, (1 if n else 0), ([1, 3] if labs else [0])
+
+
+def test_production_two_steps_sampled():
+    import torch
+    S, P, cfg = solver()
+    mz, mt = cfg.m_z, cfg.m_theta
+    rng = np.random.Generator(np.random.PCG64(21))
+    picks = [(0, 0), (0, 1), (1, 0), (mz // 2 - 1, mt - 1)]
+    picks += [(int(rng.integers(mz // 2)), int(rng.integers(mt))) for _ in range(40)]
+    cols = [(s, n) for labs, n in picks for s in ([labs] if labs == 0 else [labs, mz - labs])]
+    si = torch.tensor([c[0] for c in cols], device="cuda")
+    ni = torch.tensor([c[1] for c in cols], device="cuda")
+
+    def at(t):
+        return t[:, :, si, ni].cpu().numpy()
+
+    u = tc_inputs.initial_state(P.r, cfg, device="cuda")
+    up = tc_inputs.initial_state(P.r, tc_inputs.Config(cfg, seed=4), device="cuda")
+    Np = S.nonlinear(up)
+    U, UP, NP = at(u), at(up), at(Np)
+    S.set_state(u, up, Np)
+    del up, Np
+    S.step(1)
+    u1, p1 = S.get_state()
+    hu, N = S.get_history()
+    assert torch.equal(hu, u)
+    del hu, u
+    U1, P1, NI = at(u1), p1[:, si, ni].cpu().numpy(), at(N)
+    del p1, N
+    torch.cuda.empty_cache()
+
+    # 1. the step on every sampled mode against the oracle's predictor-
+    #    corrector (its N^i is the library's, checked on sampled planes above)
+    T = oracle.Problem(cfg.n_r, 2, 4, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+    TJ = _node_jittered(T, 5)
+    eu = ep = fu = fp = 0.0
+    k = 0
+    for labs, n in picks:
+        ns = 1 if labs == 0 else 2
+        refs = []
+        for base in (T, TJ):
+            Q, nq, sq = _mode_problem(base, labs, n, cfg.k_theta, cfg.k_z)
+            ins = [Q.zeros(3) for _ in range(4)]
+            for src, dst in zip((U, UP, NI, NP), ins):
+                for m in range(ns):
+                    dst[:, :, sq[m], nq] = src[:, :, k + m]
+            un, pn = scheme.predictor_corrector(Q, ins[2], ins[3], ins[0], ins[1])
+            refs.append((un[:, :, sq, nq], pn[:, sq, nq]))
+        (ru, rp), (ju, jp) = refs
+        gu, gp = U1[:, :, k:k + ns], P1[:, k:k + ns]
+        nu_, np_ = np.sum(np.abs(ru) ** 2), np.sum(np.abs(rp) ** 2)
+        eu += np.sum(np.abs(gu - ru) ** 2) / nu_
+        fu += np.sum(np.abs(ju - ru) ** 2) / nu_
+        ep += np.sum(np.abs(gp - rp) ** 2) / np_
+        fp += np.sum(np.abs(jp - rp) ** 2) / np_
+        k += ns
+    eu, fu, ep, fp = (np.sqrt(v / len(picks)) for v in (eu, fu, ep, fp))
+    print(f"production step, {len(picks)} sampled modes: u rel_l2 {eu:.2e} (one-ulp node floor {fu:.1e}), "
+          f"p rel_l2 {ep:.2e} (floor {fp:.1e})")
+    assert eu <= max(20 * fu, 1e-12) and ep <= max(20 * fp, 1e-10)
+
+    # 2. a second step: its nonlinear term uses the curl of u^{i+1} formed by
+    #    the first step's last sweep; it must equal the standalone nonlinear
+    #    term of u^{i+1} (same arithmetic) and the oracle on sampled planes.
+    #    The floor is the largest spread over three one-ulp draws of D1: a
+    #    single draw can leave a row nearly unchanged (its weights sum to
+    #    zero, so equal signs only rescale the derivative by 1 + eps)
+    S.step(1)
+    hu, N1 = S.get_history()
+    assert torch.equal(hu, u1)
+    del hu
+    Ns = S.nonlinear(u1)
+    fused = float(torch.linalg.vector_norm(N1 - Ns) / torch.linalg.vector_norm(Ns))
+    print(f"production second step: fused-curl nonlinear term vs standalone, whole field rel_l2={fused:.2e}")
+    assert fused < 1e-13
+    del Ns
+    Qs = [_jittered(P, seed) for seed in (23, 24, 25)]
+    num = den = 0.0
+    for j in (0, 3, 256, 511):
+        lo, hi = max(0, j - 4), min(cfg.n_r - 1, j + 4)
+        window = u1[:, lo:hi + 1].cpu().numpy()
+        ref = nl.nonlinear_rot_at(P, window, j)
+        floor = max(np.linalg.norm(nl.nonlinear_rot_at(Q, window, j) - ref) for Q in Qs) / np.linalg.norm(ref)
+        got = N1[:, j].cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"production second-step nonlinear plane {j}: rel_l2={err:.2e} (one-ulp D1 floor {floor:.2e})")
+        assert err <= max(20.0 * floor, 1e-12)
+        num += np.sum(np.abs(got - ref) ** 2)
+        den += np.sum(np.abs(ref) ** 2)
+    assert np.sqrt(num / den) < 1e-11
+    assert S.check_finite()
+    del u1, N1
     torch.cuda.empty_cache()

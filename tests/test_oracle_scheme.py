@@ -172,3 +172,27 @@ def test_axisymmetric_onset_brackets_textbook_value():
                 E.append(dg.perturbation_energy(P, u))
         rates.append(np.polyfit(np.arange(len(E)) * 50 * P.dt, np.log(E), 1)[0])
     assert rates[0] < 0 < rates[1], rates
+
+
+def test_one_mode_problem_reproduces_full_step():
+    # the production-size step test checks sampled modes with one-mode
+    # problems (grid m_theta = 2, m_z = 4, wavenumbers rescaled so that a
+    # stored slot carries the mode's a and b); on a small grid they must
+    # give exactly what the full predictor-corrector gives, mode by mode
+    from test_gpu_production import _mode_problem
+    P = oracle.Problem(24, 6, 10, 0.6, 80.0, -20.0, 1e-3, k_theta=1.5, k_z=0.8)
+    sh = (3, P.n_r, P.m_z, P.m_theta)
+    u, up, N, Np = (tc_inputs.random_state(sh, s) for s in (1, 2, 3, 4))
+    ref_u, ref_p = scheme.predictor_corrector(P, N, Np, u, up)
+    T = oracle.Problem(24, 2, 4, 0.6, 80.0, -20.0, 1e-3)
+    for labs in range(P.m_z // 2):
+        for n in range(P.m_theta):
+            slots = [labs] if labs == 0 else [labs, P.m_z - labs]
+            Q, nq, sq = _mode_problem(T, labs, n, P.k_theta, P.k_z)
+            ins = [Q.zeros(3) for _ in range(4)]
+            for src, dst in zip((u, up, N, Np), ins):
+                for m, s in enumerate(slots):
+                    dst[:, :, sq[m], nq] = src[:, :, s, n]
+            un, pn = scheme.predictor_corrector(Q, ins[2], ins[3], ins[0], ins[1])
+            assert np.array_equal(un[:, :, sq, nq], ref_u[:, :, slots, n])
+            assert np.array_equal(pn[:, sq, nq], ref_p[:, slots, n])
