@@ -2,7 +2,8 @@
 checkpointed gradient against the oracle's gradient and against central
 finite differences of the GPU forward map (the differentiation workload:
 N_r = 64, 128 x 128 physical, Re_i = 1000, T = 400 steps, checkpoints every
-20 steps)."""
+20 steps), and the adjoint step on the production planes against the
+forward step by the dot-product identity."""
 import numpy as np
 import pytest
 
@@ -83,3 +84,68 @@ def test_differentiation_workload_gradient_vs_finite_differences():
     print(f"J = {J:.10e}; worst over 8 directions: {worst:.2e}")
     assert worst < 1e-6
     S.close()
+
+
+def test_adjoint_step_at_scale_dot_product():
+    """The adjoint step at the size the benchmark times it (the production
+    planes, 1536 x 1536 dealiased, with N_r = 256), where the oracle cannot
+    run: checked against the library's own forward step by the identity
+    <ybar, J dx> = <J^T ybar, dx>.  The step is exactly quadratic in its
+    inputs (N is bilinear in u, everything else affine), so the central
+    difference (F(x + d) - F(x - d)) / 2 is J d up to rounding, for a
+    perturbation of any size.  Each of the three input cotangents is tested
+    by its own perturbation; the discrepancy is measured against the
+    Cauchy-Schwarz scale |ybar| |J d|, of which the inner product itself is
+    ~1 / sqrt(#coefficients) ~ 4e-5 for these random fields."""
+    import torch
+    from paper_1311_2481_amd import Solver
+    cfg = tc_inputs.Config(tc_inputs.CONFIGS["production"])
+    n_r = 256
+    c = tc_inputs.Config(cfg, n_r=n_r)
+    S = Solver(n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt,
+               k_theta=cfg.k_theta, k_z=cfg.k_z, alpha=cfg.alpha)
+    try:
+        r = S.radial_nodes()
+        shape = (3, n_r, cfg.m_z, cfg.m_theta)
+        x = [tc_inputs.initial_state(r, c, device="cuda"),
+             tc_inputs.initial_state(r, tc_inputs.Config(c, seed=4), device="cuda")]
+        x.append(S.nonlinear(x[1]))
+        ybar = tc_inputs.random_field_torch((9,) + shape[1:], 41, "cuda")
+        xbar = S.step_adjoint(torch.cat([x[0], x[1]]), ybar)
+
+        def inner(a, b):
+            return float(torch.vdot(a.flatten(), b.flatten()).real)
+
+        def norm(a):
+            return float(torch.linalg.vector_norm(a))
+
+        def forward(k, d):
+            args = list(x)
+            args[k] = x[k] + d
+            S.set_state(*args)
+            S.step(1)
+            u1 = S.get_state(with_pressure=False)
+            return u1, S.get_history()[1]
+
+        for k, name in enumerate(("u^i", "u^{i-1}", "N^{i-1}")):
+            d = tc_inputs.random_field_torch(shape, 50 + k, "cuda") * (0.1 * norm(x[k]) / np.sqrt(x[k].numel()))
+            up_, Np_ = forward(k, d)
+            um_, Nm_ = forward(k, -d)
+            Ju, JN = 0.5 * (up_ - um_), 0.5 * (Np_ - Nm_)
+            del up_, Np_, um_, Nm_
+            lhs = inner(ybar[0:3], Ju) + inner(ybar[6:9], JN)
+            sq = norm(Ju) ** 2 + norm(JN) ** 2
+            if k == 0:                      # u^i is also an output (the history)
+                lhs += inner(ybar[3:6], d)
+                sq += norm(d) ** 2
+            rhs = inner(xbar[3 * k:3 * k + 3], d)
+            scale = norm(ybar) * np.sqrt(sq)
+            rel = abs(lhs - rhs) / scale
+            print(f"adjoint at scale, cotangent of {name}: <ybar, J d> = {lhs:.12e}, <J^T ybar, d> = {rhs:.12e}, "
+                  f"|difference| / (|ybar| |J d|) = {rel:.2e} (inner product itself {abs(lhs) / scale:.1e})")
+            assert rel < 1e-14 and abs(lhs - rhs) <= 1e-9 * abs(lhs)
+            del d, Ju, JN
+        assert torch.all(xbar[:, :, cfg.m_z // 2] == 0)
+    finally:
+        S.close()
+        torch.cuda.empty_cache()
