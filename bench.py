@@ -254,7 +254,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--stable-dt", type=float, default=None,
-                    help="also time 10 FP64 steps at this dt (default 5e-8 for the production workload, else off; 0: off)")
+                    help="also time 10 steps (FP64, and FP32-bulk unless --no-fp32) at this dt "
+                         "(default 5e-8 for the production workload, else off; 0: off)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -299,10 +300,19 @@ def main():
         stable = {"dt": args.stable_dt, "steps": 10, "warmup": 2, "ms_per_step": round(st["seconds"] / 10 * 1e3, 3),
                   "finite_after_run": st["finite"], "cfl_bound_initial": round(st["cfl0"], 4),
                   "perturbation_energy_after": st["diag"]["perturbation_energy"]}
-    f32 = None
+    f32 = stable32 = None
     if not args.no_fp32:
         print("[bench] FP32-bulk step", file=sys.stderr, flush=True)
         f32 = run_gpu(cfg, "fp32_bulk", args.steps, args.warmup, u0)
+        if stable:
+            print(f"[bench] FP32-bulk step at dt={args.stable_dt:g}", file=sys.stderr, flush=True)
+            st = run_gpu(cs, "fp32_bulk", 10, 2, u0)
+            e64 = stable["perturbation_energy_after"]
+            e32 = st["diag"]["perturbation_energy"]
+            stable32 = {"dt": args.stable_dt, "steps": 10, "warmup": 2,
+                        "ms_per_step": round(st["seconds"] / 10 * 1e3, 3), "finite_after_run": st["finite"],
+                        "perturbation_energy_after": e32,
+                        "perturbation_energy_rel_diff_vs_fp64": abs(e32 - e64) / abs(e64)}
 
     pts = cfg.n_r * 2 * cfg.m_theta * cfg.m_z
     sps = args.steps / f64["seconds"]
@@ -348,7 +358,7 @@ def main():
         s32 = args.steps / f32["seconds"]
         out["fp32_bulk"] = {"value": round(s32, 4), "unit": "steps/s", "grid_pt_updates_per_s": round(s32 * pts, 1),
                             "ms_per_step": round(1e3 / s32, 3), "speedup_vs_fp64": round(s32 / sps, 3),
-                            "finite_after_run": f32["finite"],
+                            "finite_after_run": f32["finite"], "stable_dt_run": stable32,
                             "kernels_ms_per_step": {k: round(v[0] * v[1] / args.steps, 4)
                                                     for k, v in f32["times"].items()}}
     out["adjoint_forward_ratio"] = None
