@@ -201,17 +201,18 @@ def adjoint_step_at_scale(cfg, n_r=256, reps=3):
             "workload": f"production planes ({2 * cfg.m_theta}x{cfg.m_z} physical) with N_r={n_r}, FP64, mean of {reps}"}
 
 
-def cpu_baseline(cfg, u0_dev, repeats=3):
-    """FP64 oracle on a bounded sample: 9 full-size radial planes of the
-    nonlinear term and the predictor-corrector for the l = 0, +-1 modes at
-    full radial resolution; extrapolated linearly to one whole step."""
+def cpu_baseline(cfg, u0_dev, repeats=5):
+    """FP64 oracle on a bounded sample (about 20 s of CPU work): 17
+    full-size radial planes of the nonlinear term and the predictor-corrector
+    for the |l| <= 3 modes at full radial resolution; extrapolated linearly
+    to one whole step."""
     import torch
     import oracle
     from oracle import scheme
     from oracle.nonlinear import WORKERS
     n_r, mt, mz = cfg.n_r, cfg.m_theta, cfg.m_z
-    # nonlinear: 9 consecutive planes, full (theta, z) size
-    k = 9
+    # nonlinear: 17 consecutive planes, full (theta, z) size
+    k = 17
     Pn = oracle.Problem(k, mt, mz, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
     slab = u0_dev[:, :k].cpu().numpy()
     oracle.nonlinear_rot(Pn, slab)  # warm-up
@@ -221,12 +222,14 @@ def cpu_baseline(cfg, u0_dev, repeats=3):
         oracle.nonlinear_rot(Pn, slab)
         tn.append(time.perf_counter() - t0)
     per_plane = float(np.median(tn)) / k
-    # predictor-corrector: slots l = 0, +-1 of every n at full radial size
-    Pm = oracle.Problem(n_r, mt, 4, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
-    idx = torch.tensor([0, 1, mz - 1], device=u0_dev.device)
-    sub = np.zeros((3, n_r, 4, mt), dtype=np.complex128)
+    # predictor-corrector: slots l = 0, +-1, +-2, +-3 of every n at full
+    # radial size (every slot of the 8-slot sample grid but its Nyquist slot,
+    # so every mode solved is counted)
+    Pm = oracle.Problem(n_r, mt, 8, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+    idx = torch.tensor([0, 1, 2, 3, mz - 3, mz - 2, mz - 1], device=u0_dev.device)
+    sub = np.zeros((3, n_r, 8, mt), dtype=np.complex128)
     sel = u0_dev.index_select(2, idx).cpu().numpy()
-    sub[:, :, [0, 1, 3]] = sel
+    sub[:, :, [0, 1, 2, 3, 5, 6, 7]] = sel
     N = sub.copy()  # stand-in nonlinear terms: the values do not change the cost
     scheme.predictor_corrector(Pm, N, N, sub, sub)  # factorisation happens here (set-up)
     tm = []
@@ -234,7 +237,7 @@ def cpu_baseline(cfg, u0_dev, repeats=3):
         t0 = time.perf_counter()
         scheme.predictor_corrector(Pm, N, 0.5 * N, sub, 0.9 * sub)
         tm.append(time.perf_counter() - t0)
-    nmodes_sample = 3 * mt
+    nmodes_sample = 7 * mt
     per_mode = float(np.median(tm)) / nmodes_sample
     t_step = per_plane * n_r + per_mode * (mz - 1) * mt
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": WORKERS, "kind": "oracle",
