@@ -6,7 +6,9 @@
 * tallest radial grid the library accepts (n_r = 4096) with few modes;
 * the zero state, whose nonlinear term and step must be exactly zero;
 * a grid too large for the device: tc_init must fail with TC_ENOMEM and
-  leave the device usable.
+  leave the device usable;
+* default dealiased grids, the curl fused into the last sweep on large
+  grids, and the wall torque where circular Couette flow exerts none.
 """
 import numpy as np
 import pytest
@@ -159,3 +161,16 @@ def test_fused_curl_matches_standalone():
     assert eu < 1e-14 and ep < 1e-13
     A.close()
     B.close()
+
+
+def test_wall_torque_undefined_without_laminar_torque():
+    # Re_i = eta Re_o: circular Couette flow is a solid-body rotation
+    # (C2 = 0) and exerts no torque, so Nu_omega has no reference: NaN,
+    # while the other diagnostics stay defined
+    from paper_1311_2481_amd import Solver
+    S = Solver(12, 3, 6, 0.5, 10.0, 20.0, 1e-3)
+    S.set_state(to_dev(tc_inputs.random_state((3, 12, 6, 3), 8)))
+    d = S.diag()
+    assert np.isnan(d["nu_inner"]) and np.isnan(d["nu_outer"])
+    assert all(np.isfinite(d[k]) for k in ("energy", "perturbation_energy", "max_div", "slip", "cfl"))
+    S.close()
