@@ -83,10 +83,10 @@ def taylor_vortex_state(m_z):
     S.step(BASE_STEPS - 5000)
     e_before = S.diag()["perturbation_energy"]
     S.step(5000)
-    e_end = S.diag()["perturbation_energy"]
+    d_end = S.diag()
     base = S.get_state(with_pressure=False)
     S.close()
-    return r, base, cfg, e_before, e_end
+    return r, base, cfg, e_before, d_end
 
 
 def growth_rate(Re, r, base, cfg, m_z):
@@ -116,11 +116,12 @@ def growth_rate(Re, r, base, cfg, m_z):
 
 
 def critical_reynolds(m_z):
-    r, base, cfg, e_before, e_end = taylor_vortex_state(m_z)
+    r, base, cfg, e_before, d_end = taylor_vortex_state(m_z)
     s_lo, q_lo = growth_rate(RE_LO, r, base, cfg, m_z)
     s_hi, q_hi = growth_rate(RE_HI, r, base, cfg, m_z)
     re_c = RE_LO - s_lo * (RE_HI - RE_LO) / (s_hi - s_lo)
-    return dict(re_c=re_c, sigma=(s_lo, s_hi), harmonic=(q_lo, q_hi), vortex_energy=(e_before, e_end))
+    return dict(re_c=re_c, sigma=(s_lo, s_hi), harmonic=(q_lo, q_hi),
+                vortex_energy=(e_before, d_end["perturbation_energy"]), nu=(d_end["nu_inner"], d_end["nu_outer"]))
 
 
 def test_wavy_vortex_onset_matches_paper():
@@ -133,6 +134,11 @@ def test_wavy_vortex_onset_matches_paper():
     # 1e-5 over the last 0.1 time units), the disturbance stayed linear, and
     # the two runs straddle the onset
     assert e_end > 1e5 and abs(e_end - e_before) < 1e-5 * e_end
+    # the settled vortices carry more angular momentum than laminar flow, the
+    # same through both cylinders
+    nu_i, nu_o = out["nu"]
+    print(f"Taylor vortex flow at Re_i = {RE_LO}: Nu_omega inner {nu_i:.8f}, outer {nu_o:.8f}")
+    assert nu_i > 1.05 and abs(nu_i - nu_o) < 1e-4 * nu_i
     assert max(out["harmonic"]) < 1e-9
     assert out["sigma"][0] < 0 < out["sigma"][1]
     assert 408.07 <= out["re_c"] <= 408.12
