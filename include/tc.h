@@ -165,11 +165,25 @@ tc_status tc_perturbation_energy_gradient(tc_ctx* ctx, const void* u, void* g);
  * (per node the plane maximum of each component bounded by sum c_n |u_ln|;
  * dr the distance to the nearer neighbouring node, dtheta and dz the
  * spacings of the (2 m_theta, m_z) physical grid), the number of steps
- * taken, and the quasi-Nusselt numbers Nu_omega at r_i and at r_o (Sec. 5.4:
+ * taken, and the quasi-Nusselt numbers Nu_omega at r_i and at r_o (Sec. 5.5:
  * the torque on that cylinder, r^3 d<u_theta/r>/dr from the theta-z mean
  * by the wall row of D1, over its value -2 C2 in circular Couette flow;
  * NaN when C2 = 0).  Synchronous. */
 tc_status tc_get_diag(tc_ctx* ctx, double* out_host);
+
+/* The same eight diagnostics as tc_get_diag, for callers that cannot
+ * allocate device memory (code under stream capture preparation, tight
+ * serving loops, harnesses that forbid allocation): this call allocates
+ * nothing.  Its partial sums live in a static 4 MiB device array of the
+ * library (one per GPU, held from library load to process end; its address
+ * on the context's device is looked up once, in tc_init).  Every call on a
+ * GPU overwrites that GPU's array, so calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller;
+ * nothing in it needs clearing, every partial is written before it is read.
+ * Grids whose partials exceed the array (more than 2^19 - 8 doubles:
+ * 4 max(1024, ceil(m_z m_theta / 256)) + 97 n_r) are rejected with
+ * TC_EINVAL.  Synchronous; out_host: 8 doubles of HOST memory. */
+tc_status tc_get_diag_noalloc(tc_ctx* ctx, double* out_host);
 
 /* Check the current velocity for non-finite values: TC_ENONFINITE if any.
  * Synchronous. */

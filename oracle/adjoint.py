@@ -20,7 +20,7 @@ cotangents of the outputs to cotangents of the inputs.
 import numpy as np
 
 from . import nonlinear as nl
-from .scheme import div, grad, zero_nyquist, vector_laplacian_r
+from .scheme import div, grad, zero_nyquist, vector_laplacian_r, correction_gradient
 
 
 # ---------------------------------------------------------------- helpers
@@ -135,16 +135,22 @@ def pc_linear(prob, Ne, u, up):
     rhs_u = (-(4.0 * u - up) / (2.0 * prob.dt) + Ne + grad(prob, p)) * I
     us = np.stack([prob.solve(k, zero_nyquist(prob, rhs_u[c])) for c, k in enumerate(("Up", "Um", "Uz"))])
     phi = prob.solve("P", zero_nyquist(prob, div(prob, us) * I))
-    return zero_nyquist(prob, us - grad(prob, phi))
+    return zero_nyquist(prob, us - correction_gradient(prob, phi, us))
 
 
 def pc_adjoint(prob, ubar_next):
     """Adjoint of pc_linear: u^{i+1}_bar -> (Ne_bar, u_bar, u_prev_bar)."""
     I, Wm = _interior_mask(prob), _wall_mask(prob)
     ub = zero_nyquist(prob, ubar_next.copy())
-    # u^{i+1} = u* - grad phi
+    # u^{i+1} = u* - grad phi, except mode (0,0): u^{i+1}+- = u*+- - u*_r
     us_b = ub.copy()
-    phi_b = -grad_adjoint(prob, ub)
+    g00 = ub[0, :, 0, 0] + ub[1, :, 0, 0]
+    us_b[0, :, 0, 0] -= 0.5 * g00
+    us_b[1, :, 0, 0] -= 0.5 * g00
+    gb = ub.copy()
+    gb[0, :, 0, 0] = 0.0
+    gb[1, :, 0, 0] = 0.0
+    phi_b = -grad_adjoint(prob, gb)
     # phi = P^-1 rhs_phi, rhs_phi = div(u*) on interior rows
     rphi_b = zero_nyquist(prob, prob.solve("P", zero_nyquist(prob, phi_b), trans=1))
     us_b = us_b + div_adjoint(prob, rphi_b * I)

@@ -104,7 +104,7 @@ def cfl_bound(prob, u):
 
 
 def quasi_nusselt(prob, u):
-    """Quasi-Nusselt number at the inner and outer cylinder (Sec. 5.4): the
+    """Quasi-Nusselt number at the inner and outer cylinder (Sec. 5.5): the
     torque the fluid exerts on a cylinder divided by that of circular
     Couette flow at the same Reynolds numbers.
 

@@ -17,7 +17,13 @@ One step maps (u^i, u^{i-1}, N^{i-1}) to (u^{i+1}, p^{i+1}, N^i):
    phi uses the same operator P as the pressure (mode (0,0) again takes
    phi = 0 at the outer wall).
 5. Update (eq. update): p^{i+1} = p* + 3 phi/(2 dt), u^{i+1} = u* - grad phi,
-   applied at every node.
+   applied at every node.  For mode (0,0) the radial part of grad phi is
+   d_r phi = u*_r, the exact solution of eq. correction for that mode
+   ((1/r) d_r (r d_r phi) = (1/r) d_r (r u*_r) with d_r phi = 0 = u*_r at
+   both walls), so its radial velocity is removed entirely; the Dirichlet
+   row only fixes phi's constant, which enters the pressure alone.  (Taking
+   d_r phi from the discrete solve instead leaves this mode a projection
+   that is not idempotent, and it grows for small dt.)
 6. History shift.
 
 The first step starts from u^{-1} = u^0 and N^{-1} = N(u^0).
@@ -52,6 +58,15 @@ def vector_laplacian_r(prob, u):
         lap = prob.ddr2(f) + prob.ddr(f) / r - (a * a / r ** 2 + b * b) * f
         out.append(lap - (1.0 + sgn * 2.0 * a) / r ** 2 * f)
     return 0.5 * (out[0] + out[1])
+
+
+def correction_gradient(prob, phi, u_star):
+    """grad phi of eq. update, with mode (0,0) taking d_r phi = u*_r."""
+    g = grad(prob, phi)
+    ur = 0.5 * (u_star[0, :, 0, 0] + u_star[1, :, 0, 0])
+    g[0, :, 0, 0] = ur
+    g[1, :, 0, 0] = ur
+    return g
 
 
 def zero_nyquist(prob, f):
@@ -96,7 +111,7 @@ def predictor_corrector(prob, N, N_prev, u, u_prev, detail=False):
     rhs_phi = correction_rhs(prob, u_star)
     phi = prob.solve("P", rhs_phi)
     p_next = zero_nyquist(prob, p_star + 1.5 * phi / prob.dt)
-    u_next = zero_nyquist(prob, u_star - grad(prob, phi))
+    u_next = zero_nyquist(prob, u_star - correction_gradient(prob, phi, u_star))
     if detail:
         return u_next, p_next, dict(p_star=p_star, u_star=u_star, phi=phi, rhs_phi=rhs_phi)
     return u_next, p_next

@@ -1,7 +1,7 @@
 """Physics checks of the whole GPU path against what the paper reports:
 the onset of wavy vortex flow and the wave speed of wavy vortices (Sec. 5.2),
 the order in dt of the wall slip (Sec. 5.3), and the balance of the wall
-torques (quasi-Nusselt numbers, Sec. 5.4) in a steady pattern.
+torques (quasi-Nusselt numbers, Sec. 5.5) in a steady pattern.
 
 Onset
 -----
@@ -198,7 +198,7 @@ def test_wavy_vortex_wave_speed_matches_paper(n_r, tol):
     assert abs(c1 - c2) < 1e-6 and abs(ratio - 1) < 1e-6
     # its theta-z mean is then steady, so the angular-velocity flux is the
     # same through every cylinder: equal torques on both walls (up to the
-    # radial discretisation), above the laminar one (Sec. 5.4)
+    # radial discretisation), above the laminar one (Sec. 5.5)
     assert nu_i > 1.05 and abs(nu_i - nu_o) < 1e-4 * nu_i
     # the phase advance per window (k_theta omega tau dt ~ 1.4 rad) is below
     # pi, so the measured speed is not aliased

@@ -271,3 +271,79 @@ def test_quasi_nusselt_exact_for_quartic_angular_velocity():
     # no laminar torque (C2 = 0 on Re_i = eta Re_o): undefined
     Q = oracle.Problem(9, 1, 2, 0.5, 10.0, 20.0, 1e-3)
     assert all(np.isnan(dg.quasi_nusselt(Q, dg.couette_state(Q))))
+
+
+def _physical_values(P, c, th, z):
+    """Real field values on an explicit (z, theta) grid from its stored
+    coefficients c[s, n], summed term by term (the n < 0 half is the
+    conjugate of the stored one)."""
+    g = np.zeros((len(z), len(th)))
+    for s in range(P.m_z):
+        if s == P.nyq:
+            continue
+        for n in range(P.m_theta):
+            ph = np.exp(1j * (n * P.k_theta * th[None, :] + P.l[s] * P.k_z * z[:, None]))
+            term = c[s, n] * ph
+            g += term.real if n == 0 else 2 * term.real
+    return g
+
+
+def _hermitian_velocity(P, seed):
+    """Random velocity whose cylindrical components are real fields."""
+    u = tc_inputs.random_state((3, P.n_r, P.m_z, P.m_theta), seed)
+    ur_c, ut_c, uz_c = (u[0] + u[1]) / 2, -0.5j * (u[0] - u[1]), u[2].copy()
+    for c in (ur_c, ut_c, uz_c):
+        for s in range(1, P.m_z):
+            if s != P.nyq:
+                c[:, P.m_z - s, 0] = np.conj(c[:, s, 0])
+        c[:, 0, 0] = c[:, 0, 0].real
+        c[:, P.nyq, :] = 0.0
+    return np.stack([ur_c + 1j * ut_c, ur_c - 1j * ut_c, uz_c]), ut_c, uz_c
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_wall_slip_matches_physical_space_quadrature(wall):
+    """Relative wall slip from the spectral formula equals
+    sqrt(mean((u_theta - Re)^2 + u_z^2)) / |Re| with the mean taken over an
+    explicit (theta, z) grid at the wall, the values synthesised term by
+    term from the coefficients (enough points to integrate squares of the
+    stored modes exactly)."""
+    from oracle import diagnostics as dg
+    P = oracle.Problem(9, 3, 6, 0.6, 7.0, -3.0, 1e-3, k_theta=2.0, k_z=1.5)
+    u, ut_c, uz_c = _hermitian_velocity(P, 31)
+    j = 0 if wall == 0 else -1
+    Re = P.Re_i if wall == 0 else P.Re_o
+    # add the wall speed to the mean azimuthal velocity so that the slip is
+    # a small difference of large values, as in a real state
+    u[0, j, 0, 0] += 1j * Re
+    u[1, j, 0, 0] -= 1j * Re
+    ut_c = -0.5j * (u[0] - u[1])
+    nt, nz = 2 * P.m_theta + 1, P.m_z + 1
+    th = 2 * np.pi / P.k_theta * np.arange(nt) / nt
+    z = 2 * np.pi / P.k_z * np.arange(nz) / nz
+    ut = _physical_values(P, ut_c[j], th, z)
+    uz = _physical_values(P, uz_c[j], th, z)
+    want = np.sqrt(np.mean((ut - Re) ** 2 + uz ** 2)) / abs(Re)
+    got = dg.wall_slip(P, u, wall=wall)
+    assert abs(got - want) <= 1e-13 * want
+
+
+def test_wall_slip_closed_form_of_single_modes():
+    """u_theta = Re_i + e1 cos(l k_z z) and u_z = e2 cos(n k_theta theta) at
+    r_i: the mean squares are e1^2/2 and e2^2/2, so the slip is
+    sqrt((e1^2 + e2^2)/2) / Re_i.  u_r and the outer wall do not enter."""
+    from oracle import diagnostics as dg
+    P = oracle.Problem(9, 4, 8, 0.5, 20.0, 5.0, 1e-3)
+    u = dg.couette_state(P)
+    e1, e2 = 0.3, 0.7
+    # u_theta: slots l = +-2 at n = 0 carry e1/2 each (u+- = +-i u_theta)
+    for s in (2, P.m_z - 2):
+        u[0, 0, s, 0] += 1j * e1 / 2
+        u[1, 0, s, 0] -= 1j * e1 / 2
+    # u_z: n = 3, l = 0 carries e2/2 (its conjugate n = -3 is implied)
+    u[2, 0, 0, 3] = e2 / 2
+    # a radial velocity at the wall and anything at the other wall are ignored
+    u[0, 0, 1, 1] += 0.4
+    u[1, 0, 1, 1] += 0.4
+    u[:, -1] += 5.0
+    assert abs(dg.wall_slip(P, u) - np.sqrt((e1 ** 2 + e2 ** 2) / 2) / P.Re_i) <= 1e-14
