@@ -185,6 +185,20 @@ tc_status tc_get_diag(tc_ctx* ctx, double* out_host);
  * TC_EINVAL.  Synchronous; out_host: 8 doubles of HOST memory. */
 tc_status tc_get_diag_noalloc(tc_ctx* ctx, double* out_host);
 
+/* The same eight diagnostics as tc_get_diag, for callers that cannot
+ * allocate device memory (code under stream capture preparation, tight
+ * serving loops, harnesses that forbid allocation): this call allocates
+ * nothing.  Its partial sums live in a static 4 MiB device array of the
+ * library (one per GPU, held from library load to process end; its address
+ * on the context's device is looked up once, in tc_init).  Every call on a
+ * GPU overwrites that GPU's array, so calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller;
+ * nothing in it needs clearing, every partial is written before it is read.
+ * Grids whose partials exceed the array (more than 2^19 - 8 doubles:
+ * 4 max(1024, ceil(m_z m_theta / 256)) + 97 n_r) are rejected with
+ * TC_EINVAL.  Synchronous; out_host: 8 doubles of HOST memory. */
+tc_status tc_get_diag_noalloc(tc_ctx* ctx, double* out_host);
+
 /* Check the current velocity for non-finite values: TC_ENONFINITE if any.
  * Synchronous. */
 tc_status tc_check_finite(tc_ctx* ctx);

@@ -41,7 +41,7 @@ class _Grid(ctypes.Structure):
 _lib = None
 EXPORTS = ["tc_init", "tc_destroy", "tc_last_error", "tc_radial_nodes", "tc_set_state", "tc_get_state",
            "tc_get_history", "tc_step", "tc_nonlinear", "tc_helmholtz_solve", "tc_helmholtz_solve_transposed",
-           "tc_step_adjoint", "tc_perturbation_energy_gradient", "tc_get_diag", "tc_check_finite", "tc_set_timing", "tc_kernel_time",
+           "tc_step_adjoint", "tc_perturbation_energy_gradient", "tc_get_diag", "tc_get_diag_noalloc", "tc_check_finite", "tc_set_timing", "tc_kernel_time",
            "tc_memory_bytes"]
 
 
@@ -69,6 +69,7 @@ def load_library(path=LIB_PATH):
     lib.tc_step_adjoint.argtypes = [vp, vp, vp, vp]
     lib.tc_perturbation_energy_gradient.argtypes = [vp, vp, vp]
     lib.tc_get_diag.argtypes = [vp, ctypes.POINTER(dbl)]
+    lib.tc_get_diag_noalloc.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.tc_check_finite.argtypes = [vp]
     lib.tc_set_timing.argtypes = [vp, i32]
     lib.tc_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]

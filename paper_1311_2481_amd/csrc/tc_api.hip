@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -140,7 +141,7 @@ void twiddles(int L, std::vector<C2<T>>& out) {
 void free_ctx(tc_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rc_dev, c->fac, c->tw_t, c->tw_z, c->twf_t, c->twf_z, c->u, c->u_prev, c->N_prev,
-                  c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax};
+                  c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax, c->diag_wr, c->diag_uc};
   for (void* p : ptrs) dev_free(p);
   for (auto& t : c->timers)
     for (auto e : t.ev) (void)hipEventDestroy(e);
@@ -357,6 +358,133 @@ __global__ void k_finite(int64_t count, const double* __restrict__ x, int* __res
 
 }  // namespace tc
 
+namespace {
+
+// ---------------------------------------------------------------- diagnostics: layout and reduction
+// Partial results of the diagnostics kernels, in one array of doubles:
+// block partials of the energy, perturbation energy, |div u| maximum and
+// slip sums, the CFL mode sums per radial node, and the theta-z mean of
+// u_theta on every node.
+struct DiagLayout {
+  int nb, nbd, np, nbc;
+  size_t ncfl, o00, total;
+};
+
+DiagLayout diag_layout(const Dims& d) {
+  DiagLayout L;
+  L.nb = 1024;
+  L.nbd = (int)((d.S + 255) / 256);
+  L.np = std::max(L.nb, L.nbd);
+  L.nbc = 32;  // blocks per radial node of the CFL sums
+  L.ncfl = (size_t)d.n_r * L.nbc * 3;
+  L.o00 = 4 * (size_t)L.np + L.ncfl;
+  L.total = L.o00 + (size_t)d.n_r;
+  return L;
+}
+
+hipError_t diag_launch(tc_ctx* c, double* part, const DiagLayout& L) {
+  const Dims& d = c->d;
+  hipLaunchKernelGGL(k_energy, dim3(L.nb), dim3(256), 0, c->stream, d, c->u, c->diag_wr, c->diag_uc, 0, part);
+  hipLaunchKernelGGL(k_energy, dim3(L.nb), dim3(256), 0, c->stream, d, c->u, c->diag_wr, c->diag_uc, 1, part + L.np);
+  hipLaunchKernelGGL(k_divmax, dim3(L.nbd), dim3(256), 0, c->stream, c->rc_dev, d, c->u, part + 2 * L.np);
+  hipLaunchKernelGGL(k_slip, dim3(L.nbd), dim3(256), 0, c->stream, d, c->u, part + 3 * L.np);
+  hipLaunchKernelGGL(k_cflsum, dim3(L.nbc, d.n_r), dim3(256), 0, c->stream, d, c->u, part + 4 * L.np);
+  hipLaunchKernelGGL(k_mean_utheta, dim3((d.n_r + 255) / 256), dim3(256), 0, c->stream, d, c->u, part + L.o00);
+  return hipGetLastError();
+}
+
+// The eight diagnostics from the partials h (layout L) and the per-node
+// constants rc.  One source for the host reduction of tc_get_diag and the
+// device one of tc_get_diag_noalloc: with contraction off, both evaluate
+// the same operations in the same order and agree bit for bit.
+__host__ __device__ void diag_reduce(const Dims& d, const DiagLayout& L, const double* h, const double* rc, double eta,
+                                     double* out) {
+#pragma clang fp contract(off)
+  const double pi = 3.14159265358979323846;
+  const double area = (2.0 * pi / d.kt) * (2.0 * pi / d.kz);
+  double E = 0, Ep = 0, dv = 0, sl = 0;
+  for (int i = 0; i < L.nb; ++i) {
+    E += h[i];
+    Ep += h[L.np + i];
+  }
+  for (int i = 0; i < L.nbd; ++i) {
+    dv = dv > h[2 * L.np + i] ? dv : h[2 * L.np + i];
+    sl += h[3 * L.np + i];
+  }
+  out[0] = 0.5 * area * E;
+  out[1] = 0.5 * area * Ep;
+  out[2] = dv;
+  out[3] = sqrt(sl) / fabs(d.Re_i == 0.0 ? 1.0 : d.Re_i);
+  // CFL bound: dt max_j (B_r/dr_j + B_theta/(r_j dtheta) + B_z/dz) on the
+  // physical grid (2 m_theta, m_z), dr_j the distance to the nearer neighbour
+  const double dth = 2.0 * pi / (d.kt * 2.0 * d.mt), dz = 2.0 * pi / (d.kz * d.mz);
+  auto R = [&](int j) { return rc[(size_t)j * RC_N + RC_R]; };
+  double cfl = 0.0;
+  for (int j = 0; j < d.n_r; ++j) {
+    double B[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < L.nbc; ++b)
+      for (int k = 0; k < 3; ++k) B[k] += h[4 * (size_t)L.np + ((size_t)j * L.nbc + b) * 3 + k];
+    double dr = HUGE_VAL;
+    if (j > 0) dr = fmin(dr, R(j) - R(j - 1));
+    if (j + 1 < d.n_r) dr = fmin(dr, R(j + 1) - R(j));
+    const double v = B[0] / dr + B[1] / (R(j) * dth) + B[2] / dz;
+    cfl = cfl > v ? cfl : v;
+  }
+  out[4] = d.dt * cfl;
+  out[5] = 0.0;  // the step count is filled in by the caller
+  // Quasi-Nusselt numbers: r^3 d<omega>/dr at each wall over its Couette
+  // value -2 C2, <omega> = <u_theta>/r, d/dr by the wall rows of D1
+  const int M = d.n_r - 1;
+  const double C2 = eta * (d.Re_i - eta * d.Re_o) / ((1.0 - eta) * (1.0 - eta * eta));
+  if (C2 == 0.0) {
+    out[6] = out[7] = NAN;
+  } else {
+    for (int w = 0; w < 2; ++w) {
+      const int j = w ? M : 0;
+      const int lo = j - HW < 0 ? 0 : j - HW, hi = j + HW > M ? M : j + HW;
+      double dw = 0.0;
+      for (int k = lo; k <= hi; ++k) dw += rc[(size_t)j * RC_N + RC_W1 + (k - j + HW)] * (h[L.o00 + k] / R(k));
+      out[6 + w] = R(j) * R(j) * R(j) * dw / (-2.0 * C2);
+    }
+  }
+}
+
+__global__ void k_diag_finish(Dims d, DiagLayout L, const double* part, const double* rc, double eta, double* out) {
+  diag_reduce(d, L, part, rc, eta, out);
+}
+
+// Scratch of tc_get_diag_noalloc: one array per GPU, from module load to
+// process end.  Host code takes its device address per device from
+// hipGetSymbolAddress (tc_init, with the context's device current) and
+// never uses the array's name.
+static __device__ __align__(256) double scratch[TC_DIAG_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of the scratch on the current device (looked up once per
+// device); nullptr if the lookup fails.
+double* scratch_address(int dev) {
+  static std::mutex m;
+  std::lock_guard<std::mutex> lk(m);
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch[dev];
+}
+
+double* diag_scratch(const tc_ctx* c) {
+  return (c->device >= 0 && c->device < MAX_DEVICES) ? g_scratch[c->device] : nullptr;
+}
+
+}  // namespace
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -475,6 +603,8 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   c->p = dev_alloc<cd>(c, FB, st);
   c->omega = dev_alloc<cd>(c, 3 * FB, st);
   c->zmax = dev_alloc<unsigned int>(c, (size_t)ZMAX_WORDS * d.n_r * sizeof(unsigned int), st);
+  c->diag_wr = dev_alloc<double>(c, (size_t)d.n_r * sizeof(double), st);
+  c->diag_uc = dev_alloc<double>(c, (size_t)d.n_r * sizeof(double), st);
   // plane batch of the nonlinear term: all planes when they fit a budget
   {
     const size_t per = inter_bytes_per_plane(c);
@@ -496,6 +626,24 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream);
   };
   up(c->rc_dev, c->rc.data(), c->rc.size() * sizeof(double));
+  // energy weights w_j r_j (trapezoid rule) and the Couette profile, for
+  // the diagnostics
+  std::vector<double> wr(d.n_r, 0.0), Uc(d.n_r);
+  {
+    for (int j = 0; j + 1 < d.n_r; ++j) {
+      const double h = c->r[j + 1] - c->r[j];
+      wr[j] += 0.5 * h;
+      wr[j + 1] += 0.5 * h;
+    }
+    const double C1 = (d.Re_o - eta * d.Re_i) / (1.0 + eta);
+    const double C2 = eta * (d.Re_i - eta * d.Re_o) / ((1.0 - eta) * (1.0 - eta * eta));
+    for (int j = 0; j < d.n_r; ++j) {
+      wr[j] *= c->r[j];
+      Uc[j] = C1 * c->r[j] + C2 / c->r[j];
+    }
+  }
+  up(c->diag_wr, wr.data(), wr.size() * sizeof(double));
+  up(c->diag_uc, Uc.data(), Uc.size() * sizeof(double));
   // twiddle tables (separate host vectors: the copies are asynchronous)
   std::vector<cd> tw_t, tw_z;
   std::vector<cf> twf_t, twf_z;
@@ -529,6 +677,13 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
     g_init_error = "zero or non-finite pivot in the banded factorisation";
     free_ctx(c);
     return TC_ESINGULAR;
+  }
+  // the allocation-free diagnostics' scratch address on this device
+  if (hipGetDevice(&c->device) != hipSuccess || !scratch_address(c->device)) {
+    (void)hipGetLastError();
+    g_init_error = "cannot look up the diagnostics scratch on this device";
+    free_ctx(c);
+    return TC_EHIP;
   }
   *out = c;
   return TC_OK;
@@ -650,88 +805,38 @@ tc_status tc_helmholtz_solve_transposed(tc_ctx* c, tc_solve_kind k, const void* 
 
 tc_status tc_get_diag(tc_ctx* c, double* out) {
   if (!c || !out) return TC_EINVAL;
-  const Dims& d = c->d;
-  // energy weights w_j r_j (trapezoid rule) and the Couette profile
-  std::vector<double> wr(d.n_r, 0.0), Uc(d.n_r);
-  for (int j = 0; j + 1 < d.n_r; ++j) {
-    const double h = c->r[j + 1] - c->r[j];
-    wr[j] += 0.5 * h;
-    wr[j + 1] += 0.5 * h;
-  }
-  const double C1 = (d.Re_o - c->eta * d.Re_i) / (1.0 + c->eta);
-  const double C2 = c->eta * (d.Re_i - c->eta * d.Re_o) / ((1.0 - c->eta) * (1.0 - c->eta * c->eta));
-  for (int j = 0; j < d.n_r; ++j) {
-    wr[j] *= c->r[j];
-    Uc[j] = C1 * c->r[j] + C2 / c->r[j];
-  }
-  const int nb = 1024;
-  const int nbd = (int)((d.S + 255) / 256);
-  const int np = std::max(nb, nbd);
-  const int nbc = 32;  // blocks per radial node of the CFL sums
-  const size_t ncfl = (size_t)d.n_r * nbc * 3;
-  // after the partial sums: the theta-z mean of u_theta on every node, for
-  // the wall torques
-  const size_t o00 = 4 * (size_t)np + ncfl, n00 = (size_t)d.n_r;
-  double *dwr = nullptr, *dUc = nullptr, *part = nullptr;
-  hipError_t e = hipMalloc(&dwr, d.n_r * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&dUc, d.n_r * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&part, (o00 + n00) * sizeof(double));
-  if (e == hipSuccess) e = hipMemcpyAsync(dwr, wr.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(dUc, Uc.data(), d.n_r * sizeof(double), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->stream, d, c->u, dwr, dUc, 0, part);
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->stream, d, c->u, dwr, dUc, 1, part + np);
-    hipLaunchKernelGGL(k_divmax, dim3(nbd), dim3(256), 0, c->stream, c->rc_dev, d, c->u, part + 2 * np);
-    hipLaunchKernelGGL(k_slip, dim3(nbd), dim3(256), 0, c->stream, d, c->u, part + 3 * np);
-    hipLaunchKernelGGL(k_cflsum, dim3(nbc, d.n_r), dim3(256), 0, c->stream, d, c->u, part + 4 * np);
-    hipLaunchKernelGGL(k_mean_utheta, dim3((d.n_r + 255) / 256), dim3(256), 0, c->stream, d, c->u, part + o00);
-    e = hipGetLastError();
-  }
-  std::vector<double> h(o00 + n00, 0.0);
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  const DiagLayout L = diag_layout(c->d);
+  double* part = nullptr;
+  hipError_t e = hipMalloc(&part, L.total * sizeof(double));
+  if (e == hipSuccess) e = diag_launch(c, part, L);
+  std::vector<double> h(L.total, 0.0);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, L.total * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(dwr);
-  (void)hipFree(dUc);
   (void)hipFree(part);
   if (e != hipSuccess) return hip_check(c, e, "tc_get_diag");
-  const double area = (2.0 * M_PI / d.kt) * (2.0 * M_PI / d.kz);
-  double E = 0, Ep = 0, dv = 0, sl = 0;
-  for (int i = 0; i < nb; ++i) { E += h[i]; Ep += h[np + i]; }
-  for (int i = 0; i < nbd; ++i) { dv = std::max(dv, h[2 * np + i]); sl += h[3 * np + i]; }
-  out[0] = 0.5 * area * E;
-  out[1] = 0.5 * area * Ep;
-  out[2] = dv;
-  out[3] = std::sqrt(sl) / std::fabs(d.Re_i == 0.0 ? 1.0 : d.Re_i);
-  // CFL bound: dt max_j (B_r/dr_j + B_theta/(r_j dtheta) + B_z/dz) on the
-  // physical grid (2 m_theta, m_z), dr_j the distance to the nearer neighbour
-  const double dth = 2.0 * M_PI / (d.kt * 2.0 * d.mt), dz = 2.0 * M_PI / (d.kz * d.mz);
-  double cfl = 0.0;
-  for (int j = 0; j < d.n_r; ++j) {
-    double B[3] = {0.0, 0.0, 0.0};
-    for (int b = 0; b < nbc; ++b)
-      for (int k = 0; k < 3; ++k) B[k] += h[4 * (size_t)np + ((size_t)j * nbc + b) * 3 + k];
-    double dr = HUGE_VAL;
-    if (j > 0) dr = std::min(dr, c->r[j] - c->r[j - 1]);
-    if (j + 1 < d.n_r) dr = std::min(dr, c->r[j + 1] - c->r[j]);
-    cfl = std::max(cfl, B[0] / dr + B[1] / (c->r[j] * dth) + B[2] / dz);
-  }
-  out[4] = d.dt * cfl;
+  diag_reduce(c->d, L, h.data(), c->rc.data(), c->eta, out);
   out[5] = (double)c->steps;
-  // Quasi-Nusselt numbers: r^3 d<omega>/dr at each wall over its Couette
-  // value -2 C2, <omega> = <u_theta>/r, d/dr by the wall rows of D1
-  const int M = d.n_r - 1;
-  if (C2 == 0.0) {
-    out[6] = out[7] = std::nan("");
-  } else {
-    auto omega = [&](int k) { return h[o00 + k] / c->r[k]; };
-    for (int w = 0; w < 2; ++w) {
-      const int j = w ? M : 0;
-      const int lo = std::max(0, j - HW), hi = std::min(M, j + HW);
-      double dw = 0.0;
-      for (int k = lo; k <= hi; ++k) dw += c->rc[(size_t)j * RC_N + RC_W1 + (k - j + HW)] * omega(k);
-      out[6 + w] = c->r[j] * c->r[j] * c->r[j] * dw / (-2.0 * C2);
-    }
+  return TC_OK;
+}
+
+tc_status tc_get_diag_noalloc(tc_ctx* c, double* out) {
+  if (!c || !out) return TC_EINVAL;
+  const DiagLayout L = diag_layout(c->d);
+  if (L.total + 8 > TC_DIAG_SCRATCH_DOUBLES)
+    return fail(c, TC_EINVAL, "tc_get_diag_noalloc: the grid needs " + std::to_string(L.total + 8) +
+                                  " doubles of scratch, more than its " + std::to_string(TC_DIAG_SCRATCH_DOUBLES));
+  double* part = diag_scratch(c);
+  if (!part) return fail(c, TC_EHIP, "tc_get_diag_noalloc: no scratch address for this device");
+  hipError_t e = diag_launch(c, part, L);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(1), 0, c->stream, c->d, L, part, c->rc_dev, c->eta,
+                       part + L.total);
+    e = hipGetLastError();
   }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, part + L.total, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "tc_get_diag_noalloc");
+  out[5] = (double)c->steps;
   return TC_OK;
 }
 

@@ -33,6 +33,9 @@ constexpr int RC_R = 0, RC_IR = 1, RC_IR2 = 2, RC_W1 = 3, RC_W2 = 12, RC_N = 21;
 constexpr int NOPS = 4, NFAC = 9;
 enum { OP_P = 0, OP_HP = 1, OP_HM = 2, OP_HZ = 3 };
 
+// Doubles of the static scratch array of tc_get_diag_noalloc (4 MiB per GPU).
+constexpr size_t TC_DIAG_SCRATCH_DOUBLES = (size_t)1 << 19;
+
 // Launch timing slots (tc_kernel_time).
 enum { TK_PC = 0, TK_CURL = 1, TK_ZINV = 2, TK_THETA = 3, TK_ZFWD = 4, TK_N = 5 };
 
@@ -95,6 +98,9 @@ struct tc_ctx {
   size_t aux_bytes = 0;
   void* inter = nullptr;     // nonlinear intermediate, batch planes
   unsigned int* zmax = nullptr;  // per-plane field magnitudes (ZMAX_WORDS n_r words)
+  double* diag_wr = nullptr;     // trapezoid weight times r on every node
+  double* diag_uc = nullptr;     // circular Couette u_theta on every node
+  int device = -1;               // HIP device the context was created on
   int batch = 0;
   size_t bytes = 0;
   int64_t steps = 0;
