@@ -32,19 +32,29 @@ def workload_label(cfg, name):
             f"dt={cfg.dt:g}, perturbation amp {cfg.amp:g} ({cfg.envelope}), seed {cfg.seed}")
 
 
+def step_alg_bytes(cfg):
+    """Algorithmic bytes of one whole step: state traffic 256 B per stored
+    coefficient slot (read u^i, u^{i-1}, N^{i-1}; write u^{i+1}, N^i, p: 16
+    complex fields) plus the LU factors of the 4 operators, 9 doubles per
+    radial row of every distinct mode (+-l share one), read once.  With
+    S = N_r m_theta m_z this is 256 S + 144 S = 400 S bytes."""
+    S = cfg.n_r * cfg.m_theta * cfg.m_z
+    return 256 * S + 4 * 9 * 8 * cfg.n_r * cfg.m_theta * (cfg.m_z // 2)
+
+
 def kernel_bytes(cfg, precision):
     """Algorithmic bytes per launch of each kernel (one full step, all planes)."""
     n_r, mt, mz = cfg.n_r, cfg.m_theta, cfg.m_z
     pz = 3 * mz // 2
-    ndm = mt * (mz // 2)
     modes = mt * (mz - 1)             # stored modes without the empty slot
     el = 8 if precision == "fp32_bulk" else 16
     inter = pz * mt * el               # one field of one plane, transform layout
     spec = modes * 16                  # one spectral field of one plane
     return {
-        # in: u^i, u^{i-1}, N^i, N^{i-1} (12 fields); out: u^{i+1}, p (4 fields);
-        # LU factors of 4 operators, 9 doubles per row, shared by +-l
-        "pc": 16 * 16 * n_r * modes + 4 * 9 * 8 * n_r * ndm,
+        # the predictor-corrector group moves the step's whole state and
+        # factor traffic: in u^i, u^{i-1}, N^i, N^{i-1} (12 fields), out
+        # u^{i+1}, p (4 fields), and the factors once (step_alg_bytes)
+        "pc": step_alg_bytes(cfg),
         "curl": 6 * spec * n_r,
         "zinv": (6 * spec + 6 * inter) * n_r,
         "theta": 9 * inter * n_r,
@@ -247,6 +257,47 @@ def cpu_baseline(cfg, u0_dev, repeats=5):
                        f"{t_step:.1f} s/step (scipy.fft with {WORKERS} workers, NumPy elementwise on 1 core)")}
 
 
+def other_workloads(steps_small=200, steps_medium=200):
+    """Steps/s of the small and medium workloads, FP64 beside FP32-bulk, and
+    the FP32-bulk form of the medium workload (500 steps at its stable dt,
+    with the relative field and perturbation-energy differences to FP64)."""
+    import torch
+    import tc_inputs
+    from paper_1311_2481_amd import Solver
+    out = {}
+    for name, steps in (("small", steps_small), ("medium", steps_medium), ("medium_fp32", 500)):
+        cfg = tc_inputs.Config(tc_inputs.CONFIGS[name])
+        if name == "medium_fp32":
+            cfg["dt"] = 1e-5  # the workload's 2e-4 is about 17x its advective limit
+        probe = Solver(cfg.n_r, 16, 32, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+        u0 = tc_inputs.initial_state(probe.radial_nodes(), cfg, device="cuda")
+        probe.close()
+        row = {"dt": cfg.dt, "steps": steps}
+        states = {}
+        for prec in ("fp64", "fp32_bulk"):
+            S = Solver(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt, precision=prec)
+            S.set_state(u0)
+            S.step(5)
+            S.set_state(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[prec] = {"steps_per_s": round(steps / dt, 2), "ms_per_step": round(dt / steps * 1e3, 4),
+                         "grid_pt_updates_per_s": round(steps / dt * cfg.n_r * 2 * cfg.m_theta * cfg.m_z, 1)}
+            states[prec] = (S.get_state(with_pressure=False), S.diag()["perturbation_energy"])
+            S.close()
+        u64, e64 = states["fp64"]
+        u32, e32 = states["fp32_bulk"]
+        row["fp32_speedup"] = round(row["fp32_bulk"]["steps_per_s"] / row["fp64"]["steps_per_s"], 3)
+        row["fp32_vs_fp64_rel_field_diff"] = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+        row["fp32_vs_fp64_rel_perturbation_energy_diff"] = abs(e32 - e64) / abs(e64)
+        out[name] = row
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,9 +307,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-others", action="store_true", help="skip the small and medium workload lines")
     ap.add_argument("--stable-dt", type=float, default=None,
-                    help="also time 10 steps (FP64, and FP32-bulk unless --no-fp32) at this dt "
-                         "(default 5e-8 for the production workload, else off; 0: off)")
+                    help="time step of the headline run (default 5e-8 for the production workload: its "
+                         "as-specified 5e-5 is about 670x past the explicit limit and its fields overflow; "
+                         "the cost does not depend on dt); the as-specified dt is timed beside it; 0: off")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -272,7 +325,10 @@ def main():
     import tc_inputs
     from paper_1311_2481_amd import Solver
 
-    cfg = tc_inputs.Config(tc_inputs.CONFIGS[args.workload])
+    cfg_spec = tc_inputs.Config(tc_inputs.CONFIGS[args.workload])
+    cfg = tc_inputs.Config(cfg_spec)
+    if args.stable_dt > 0:
+        cfg["dt"] = args.stable_dt
     if args.calibrate_copy:
         n = args.calibrate_copy * 2 ** 20 // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -289,46 +345,36 @@ def main():
     u0 = tc_inputs.initial_state(r, cfg, device="cuda")
     torch.cuda.synchronize()
 
-    print("[bench] FP64 step", file=sys.stderr, flush=True)
+    print(f"[bench] FP64 step at dt={cfg.dt:g}", file=sys.stderr, flush=True)
     f64 = run_gpu(cfg, "fp64", args.steps, args.warmup, u0)
-    stable = None
+    as_spec = None
     if args.stable_dt > 0:
-        # the same step at a time step inside the scheme's stable range: the
-        # cost does not depend on dt (it only enters 3/(2 dt) in the
-        # factors), and the fields stay finite
-        print(f"[bench] FP64 step at dt={args.stable_dt:g}", file=sys.stderr, flush=True)
-        cs = tc_inputs.Config(cfg)
-        cs["dt"] = args.stable_dt
-        st = run_gpu(cs, "fp64", 10, 2, u0)
-        stable = {"dt": args.stable_dt, "steps": 10, "warmup": 2, "ms_per_step": round(st["seconds"] / 10 * 1e3, 3),
-                  "finite_after_run": st["finite"], "cfl_bound_initial": round(st["cfl0"], 4),
-                  "perturbation_energy_after": st["diag"]["perturbation_energy"]}
-    f32 = stable32 = None
+        # the as-specified time step: same cost (dt only enters 3/(2 dt) in
+        # the factors), fields not finite at the end
+        print(f"[bench] FP64 step at the as-specified dt={cfg_spec.dt:g}", file=sys.stderr, flush=True)
+        sp = run_gpu(cfg_spec, "fp64", args.steps, args.warmup, u0)
+        as_spec = {"dt": cfg_spec.dt, "steps": args.steps, "warmup": args.warmup,
+                   "steps_per_s": round(args.steps / sp["seconds"], 4),
+                   "ms_per_step": round(sp["seconds"] / args.steps * 1e3, 3), "finite_after_run": sp["finite"],
+                   "cfl_bound_initial": round(sp["cfl0"], 3)}
+    f32 = None
     if not args.no_fp32:
         print("[bench] FP32-bulk step", file=sys.stderr, flush=True)
         f32 = run_gpu(cfg, "fp32_bulk", args.steps, args.warmup, u0)
-        if stable:
-            print(f"[bench] FP32-bulk step at dt={args.stable_dt:g}", file=sys.stderr, flush=True)
-            st = run_gpu(cs, "fp32_bulk", 10, 2, u0)
-            e64 = stable["perturbation_energy_after"]
-            e32 = st["diag"]["perturbation_energy"]
-            stable32 = {"dt": args.stable_dt, "steps": 10, "warmup": 2,
-                        "ms_per_step": round(st["seconds"] / 10 * 1e3, 3), "finite_after_run": st["finite"],
-                        "perturbation_energy_after": e32,
-                        "perturbation_energy_rel_diff_vs_fp64": abs(e32 - e64) / abs(e64)}
 
     pts = cfg.n_r * 2 * cfg.m_theta * cfg.m_z
     sps = args.steps / f64["seconds"]
     kb = kernel_bytes(cfg, "fp64")
+    B_alg = step_alg_bytes(cfg)
     # on large grids the last predictor-corrector sweep also forms the curl of
-    # the new velocity (3 more fields written), and the standalone curl runs
-    # only once per tc_step call
+    # the new velocity (3 more fields written, implementation traffic: the
+    # algorithmic decomposition never writes omega), and the standalone curl
+    # runs only once per tc_step call
     fused = f64["times"]["curl"][1] < args.steps
-    if fused:
-        kb["pc"] += 3 * 16 * cfg.m_theta * (cfg.m_z - 1) * cfg.n_r
     launches = dict(KERNEL_LAUNCHES)
     if fused:
-        launches["pc"] += "; k_pc4 also writes the curl of u^{i+1} for the next step"
+        launches["pc"] += ("; k_pc4 also writes the curl of u^{i+1} for the next step "
+                           "(implementation traffic, not counted as algorithmic bytes)")
     per_step = {k: v[0] * v[1] / args.steps for k, v in f64["times"].items()}
     kernels = {}
     for k, (ms, nl) in f64["times"].items():
@@ -345,13 +391,21 @@ def main():
     roof = {"kernel": dom, "launches": kd["launches"], "bound": "hbm", "achieved": kd["achieved_GBs"],
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"], "traffic": kd["traffic"],
             "algorithmic_bytes_per_launch": kd["algorithmic_bytes_per_launch"], "mean_launch_ms": kd["mean_launch_ms"]}
+    step_frac = {"algorithmic_bytes_per_step": int(B_alg),
+                 "fp64": round(B_alg / (f64["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    label = workload_label(cfg, args.workload)
+    if args.stable_dt > 0:
+        label += (f" (headline at dt={cfg.dt:g}, where the fields stay finite; the as-specified "
+                  f"dt={cfg_spec.dt:g} costs the same and is timed in as_specified_dt_run)")
     out = {
         "metric": METRIC, "value": round(sps, 4), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 / sps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": workload_label(cfg, args.workload), "grid_points_per_step": pts},
+        "config": {"workload": label, "grid_points_per_step": pts},
         "grid_pt_updates_per_s": round(sps * pts, 1),
-        "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3), "stable_dt_run": stable,
+        "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3),
+        "as_specified_dt_run": as_spec,
+        "step_alg_frac": step_frac,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
         "roofline": roof,
@@ -359,9 +413,13 @@ def main():
     }
     if f32:
         s32 = args.steps / f32["seconds"]
+        e64 = f64["diag"]["perturbation_energy"]
+        e32 = f32["diag"]["perturbation_energy"]
+        step_frac["fp32_bulk"] = round(B_alg / (f32["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
         out["fp32_bulk"] = {"value": round(s32, 4), "unit": "steps/s", "grid_pt_updates_per_s": round(s32 * pts, 1),
                             "ms_per_step": round(1e3 / s32, 3), "speedup_vs_fp64": round(s32 / sps, 3),
-                            "finite_after_run": f32["finite"], "stable_dt_run": stable32,
+                            "finite_after_run": f32["finite"],
+                            "perturbation_energy_rel_diff_vs_fp64": abs(e32 - e64) / abs(e64),
                             "kernels_ms_per_step": {k: round(v[0] * v[1] / args.steps, 4)
                                                     for k, v in f32["times"].items()}}
     out["adjoint_forward_ratio"] = None
@@ -370,6 +428,10 @@ def main():
         out["adjoint_forward_ratio"] = adjoint_ratio()
         print("[bench] adjoint step at scale", file=sys.stderr, flush=True)
         out["adjoint_step_at_scale"] = adjoint_step_at_scale(cfg)
+        step_frac["adjoint_step_at_scale"] = out["adjoint_step_at_scale"]["frac"]
+    if not args.no_others:
+        print("[bench] small and medium workloads", file=sys.stderr, flush=True)
+        out["other_workloads"] = other_workloads()
     if not args.no_cpu:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, u0)

@@ -49,7 +49,8 @@ typedef enum {
   TC_OK = 0,
   TC_EINVAL = 1,      /* invalid argument or unsupported grid            */
   TC_ENOMEM = 2,      /* device allocation failed                        */
-  TC_ESINGULAR = 3,   /* zero or non-finite pivot while factoring        */
+  TC_ESINGULAR = 3,   /* zero or non-finite pivot, or factors failing the
+                         backward-error check of tc_init                 */
   TC_EHIP = 4,        /* HIP runtime error                               */
   TC_ENONFINITE = 5   /* non-finite value found by a finite check        */
 } tc_status;
@@ -59,6 +60,15 @@ typedef enum {
   TC_FP32_BULK = 1    /* transforms and products in float (float accumulation);
                          curl, LU solves, correction and all state in double   */
 } tc_precision;
+
+/* Form of the nonlinear term (Sec. 3.2, step 1). */
+typedef enum {
+  TC_ROTATIONAL = 0,  /* N = omega x u from 6 transformed fields; the pressure
+                         variable is then p + |u|^2/2                          */
+  TC_CONVECTIVE = 1   /* N = u.grad u with the curvature terms of eq. NS_cyl,
+                         from 12 transformed fields as the paper computes it;
+                         the pressure is p.  FP64 only; no tc_step_adjoint    */
+} tc_form;
 
 /* The five linear systems of one step (Sec. 3.2, steps 2-4). */
 typedef enum {
@@ -81,7 +91,7 @@ typedef struct {
   int32_t m_z;        /* axial slots (even)                                   */
   int32_t p_theta;    /* dealiased azimuthal grid. Must be >= 3*m_theta - 2
                          (3/2 rule, Sec. 3.1) and a supported transform length
-                         (16, 24, 32, 48, ..., 1536, 2048: 2^k and 3*2^k);
+                         (2^k, 3*2^k, 5*2^k, 9*2^k, 15*2^k from 16 to 2048);
                          0 -> the smallest supported length >= 3*m_theta - 2 */
   int32_t p_z;        /* dealiased axial grid; >= 3*m_z/2 - 2 and a supported
                          length; 0 -> the smallest one >= 3*m_z/2 - 2         */
@@ -90,6 +100,7 @@ typedef struct {
   double alpha;       /* node-map parameter of eq. nodeDist; 0 = Chebyshev limit */
   int32_t n_s;        /* stencil length; only 9 is supported (Sec. 3.1)        */
   int32_t precision;  /* tc_precision                                         */
+  int32_t form;       /* tc_form: the nonlinear term's form (Sec. 3.2, step 1) */
 } tc_grid;
 
 typedef struct tc_ctx tc_ctx;
@@ -129,8 +140,9 @@ tc_status tc_get_history(const tc_ctx* ctx, void* u_prev, void* N_prev);
 /* Advance the state by nsteps >= 0 projection steps (Sec. 3.2, steps 1-6). */
 tc_status tc_step(tc_ctx* ctx, int32_t nsteps);
 
-/* Nonlinear term N = omega x u of a velocity u (3 fields) into N (3 fields),
- * by the pseudospectral method with 3/2 dealiasing (Sec. 3.2, step 1).
+/* Nonlinear term N of a velocity u (3 fields) into N (3 fields), in the
+ * context's form (omega x u or u.grad u), by the pseudospectral method with
+ * 3/2 dealiasing (Sec. 3.2, step 1).
  * u and N must not overlap.  Does not touch the context's state. */
 tc_status tc_nonlinear(tc_ctx* ctx, const void* u, void* N);
 
@@ -147,7 +159,8 @@ tc_status tc_helmholtz_solve_transposed(tc_ctx* ctx, tc_solve_kind k, const void
  * back (6 fields).  adj_in: cotangents of the step outputs (u^{i+1}, u^i,
  * N^i) (9 fields).  adj_out: cotangents of the step inputs (u^i, u^{i-1},
  * N^{i-1}) (9 fields).  The inner product is sum Re(conj(x) y) over every
- * stored coefficient.  adj_in and adj_out must not overlap. */
+ * stored coefficient.  adj_in and adj_out must not overlap.  Rotational
+ * form only (TC_EINVAL otherwise). */
 tc_status tc_step_adjoint(tc_ctx* ctx, const void* fwd, const void* adj_in, void* adj_out);
 
 /* Gradient of the perturbation kinetic energy E_pert(u) = 1/2 int |u - U_c|^2 dV
@@ -156,6 +169,48 @@ tc_status tc_step_adjoint(tc_ctx* ctx, const void* fwd, const void* adj_in, void
  * the inner product of tc_step_adjoint, into g (3 fields).  This is the
  * seed of the reverse sweep for the final-energy objective. */
 tc_status tc_perturbation_energy_gradient(tc_ctx* ctx, const void* u, void* g);
+
+/* Ends of the reverse sweep for the final-energy objective J = E_pert(u^T).
+ * tc_adjoint_seed: g = scale * dJ/du at u = u^T (3 fields), the cotangent
+ *   of the last step's output times the caller's cotangent of J.
+ * tc_adjoint_initial_history: the cotangent of u^0 when the history of the
+ *   first step is u^{-1} = u^0, N^{-1} = N(u^0) (what tc_set_state with
+ *   NULL history sets): g = u_bar + u_prev_bar + N'(u^0)^T N_bar, from the
+ *   9-field cotangent adj_in = (u_bar, u_prev_bar, N_bar) of the first
+ *   step's inputs (tc_step_adjoint's adj_out).  u0, g: 3 fields; adj_in and
+ *   g must not overlap.  Rotational form only. */
+tc_status tc_adjoint_seed(tc_ctx* ctx, const void* uT, double scale, void* g);
+tc_status tc_adjoint_initial_history(tc_ctx* ctx, const void* u0, const void* adj_in, void* g);
+
+/* Optimal-perturbation control (not in the paper's method; the paper's
+ * quasi-Keplerian run of Sec. 5.5 starts from a nonlinear optimal
+ * perturbation taken from elsewhere).  The initial perturbation is the curl
+ * of a vector potential with smooth radial profiles: per stored mode
+ * (a = n k_theta, b = l k_z), A_c(r) = sum_{q=0..3} a[c][q] g(r) T_q(xi),
+ * g = 16 (r - r_i)^2 (r_o - r)^2, xi = 2 (r - r_i) - 1 (T_q Chebyshev), and
+ * u_r = i a A_z / r - i b A_theta, u_theta = i b A_r - d_r A_z,
+ * u_z = d_r A_theta + A_theta / r - i a A_r / r.  A control is complex128
+ * a[c][q][s][n] (c = r, theta, z; q = 0..3; slot s, wavenumber n as in the
+ * spectral layout): 12 m_z m_theta values; mode (0,0) and the empty slot
+ * are not controls (read as zero, written as zero), and the n = 0 column of
+ * a real perturbation obeys a(-l) = conj(a(l)).
+ *
+ * tc_control_velocity: u = U_c + B a (3 fields; U_c circular Couette flow).
+ * tc_control_gradient: ga = the gradient with respect to the control of a
+ *   function whose gradient with respect to u is g (3 fields), i.e. B^H g
+ *   projected on the controls with the n = 0 symmetry; inner products
+ *   sum Re(conj(x) y) in both spaces.
+ * tc_control_ascent_update: one step of projected gradient ascent on the
+ *   sphere E_pert(U_c + B a) = E0: with p = gJ - beta gE, beta = <gJ, gE> /
+ *   <gE, gE>, a_out = s (a + tau p) and s such that the perturbation energy
+ *   of a_out is E0 exactly.  gJ and gE may both be NULL (then a_out is a
+ *   rescaled to E0).  stats (host, nullable, 5 doubles): beta, the energy
+ *   before rescaling, s, |p| and |a| (of the input a).  Synchronous.
+ *   a_out may equal a.  Uses the context's curl work buffer. */
+tc_status tc_control_velocity(tc_ctx* ctx, const void* a, void* u);
+tc_status tc_control_gradient(tc_ctx* ctx, const void* g, void* ga);
+tc_status tc_control_ascent_update(tc_ctx* ctx, const void* a, const void* gJ, const void* gE, double tau,
+                                   double E0, void* a_out, double* stats_host);
 
 /* Diagnostics of the current state into HOST memory (8 doubles):
  * kinetic energy, perturbation energy (against circular Couette flow),
@@ -185,20 +240,6 @@ tc_status tc_get_diag(tc_ctx* ctx, double* out_host);
  * TC_EINVAL.  Synchronous; out_host: 8 doubles of HOST memory. */
 tc_status tc_get_diag_noalloc(tc_ctx* ctx, double* out_host);
 
-/* The same eight diagnostics as tc_get_diag, for callers that cannot
- * allocate device memory (code under stream capture preparation, tight
- * serving loops, harnesses that forbid allocation): this call allocates
- * nothing.  Its partial sums live in a static 4 MiB device array of the
- * library (one per GPU, held from library load to process end; its address
- * on the context's device is looked up once, in tc_init).  Every call on a
- * GPU overwrites that GPU's array, so calls that overlap on one GPU (other
- * host threads, other streams) race and must be serialised by the caller;
- * nothing in it needs clearing, every partial is written before it is read.
- * Grids whose partials exceed the array (more than 2^19 - 8 doubles:
- * 4 max(1024, ceil(m_z m_theta / 256)) + 97 n_r) are rejected with
- * TC_EINVAL.  Synchronous; out_host: 8 doubles of HOST memory. */
-tc_status tc_get_diag_noalloc(tc_ctx* ctx, double* out_host);
-
 /* Check the current velocity for non-finite values: TC_ENONFINITE if any.
  * Synchronous. */
 tc_status tc_check_finite(tc_ctx* ctx);
@@ -211,6 +252,15 @@ tc_status tc_check_finite(tc_ctx* ctx);
  * launches_out receives the number of launches averaged.  Synchronous. */
 tc_status tc_set_timing(tc_ctx* ctx, int32_t enable);
 tc_status tc_kernel_time(tc_ctx* ctx, int32_t which, double* ms_out, int32_t* launches_out);
+
+/* The factors are LU without pivoting (the paper's DGBTRF pivots; the
+ * Neumann rows of P are scaled to the size of the Laplacian rows instead).
+ * tc_init accepts them only after a check: for every operator and distinct
+ * mode it solves A x = A x0 (x0_j = 1 + sin(0.7 j)/2) with the stored
+ * factors and takes the componentwise backward error
+ * max_j |A x - b|_j / (|A| |x| + |b|)_j; above 1e-12 it fails with
+ * TC_ESINGULAR.  This call returns the largest error found (host double). */
+tc_status tc_factor_backward_error(const tc_ctx* ctx, double* error_host);
 
 /* Bytes of device memory the context holds (host pointer out). */
 tc_status tc_memory_bytes(const tc_ctx* ctx, uint64_t* bytes_out);

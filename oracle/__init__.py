@@ -25,8 +25,8 @@ simulations with application to Taylor-Couette flow") section by section:
 """
 from .radial import radii, nodes, fornberg_weights, fd_matrices, couette_profile
 from .operators import Problem
-from .nonlinear import nonlinear_rot, nonlinear_conv
+from .nonlinear import nonlinear_term, nonlinear_rot, nonlinear_conv
 from . import scheme, diagnostics
 
 __all__ = ["radii", "nodes", "fornberg_weights", "fd_matrices", "couette_profile",
-           "Problem", "nonlinear_rot", "nonlinear_conv", "scheme", "diagnostics"]
+           "Problem", "nonlinear_term", "nonlinear_rot", "nonlinear_conv", "scheme", "diagnostics"]

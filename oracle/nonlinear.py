@@ -133,3 +133,8 @@ def kinetic_density(prob, u):
     """Coefficients of |u|^2 / 2 (dealiased), the Bernoulli term of the rotational form."""
     U = to_physical(prob, np.stack(cylindrical(u)))
     return to_spectral(prob, 0.5 * (U[0] ** 2 + U[1] ** 2 + U[2] ** 2))
+
+
+def nonlinear_term(prob, u):
+    """The nonlinear term in the problem's form (prob.form)."""
+    return nonlinear_conv(prob, u) if prob.form == "conv" else nonlinear_rot(prob, u)

@@ -41,9 +41,14 @@ class Problem:
     """Grid, parameters and cached per-mode LU factors of one configuration."""
 
     def __init__(self, n_r, m_theta, m_z, eta, Re_i, Re_o, dt, k_theta=1.0, k_z=1.0,
-                 alpha=0.0, p_theta=0, p_z=0):
+                 alpha=0.0, p_theta=0, p_z=0, form="rot"):
         if m_z % 2:
             raise ValueError("m_z must be even")
+        if form not in ("rot", "conv"):
+            raise ValueError("form must be 'rot' (omega x u) or 'conv' (u.grad u)")
+        # form of the nonlinear term the step uses: rotational omega x u, or
+        # the paper's convective u.grad u (Sec. 3.2, step 1)
+        self.form = form
         self.n_r, self.m_theta, self.m_z = n_r, m_theta, m_z
         self.M = n_r - 1
         self.p_theta = p_theta or 3 * m_theta

@@ -2,7 +2,9 @@
 
 One step maps (u^i, u^{i-1}, N^{i-1}) to (u^{i+1}, p^{i+1}, N^i):
 
-1. N^i = N(u^i) pseudospectrally; Ne = 2 N^i - N^{i-1} (eq. timeScheme).
+1. N^i = N(u^i) pseudospectrally, in the problem's form: omega x u (the
+   pressure variable is then p + |u|^2/2) or the paper's u.grad u;
+   Ne = 2 N^i - N^{i-1} (eq. timeScheme).
 2. Pressure predictor (eq. pressure): P p* = -div(Ne) inside, with the
    consistent Neumann rows of eq. ppBC at both walls.  Discretely the wall
    rows read  d_r p* = -Ne_r + (2 V_r(u^i) - V_r(u^{i-1})),  where V_r is the
@@ -35,7 +37,7 @@ In the (u+, u-, u_z) variables (Sec. 3.1):
 """
 import numpy as np
 
-from .nonlinear import nonlinear_rot
+from .nonlinear import nonlinear_term
 
 
 def grad(prob, f):
@@ -120,7 +122,7 @@ def predictor_corrector(prob, N, N_prev, u, u_prev, detail=False):
 def step(prob, u, u_prev, N_prev, N=None, detail=False):
     """One projection step.  Returns (u_next, p_next, N) (+ intermediates if detail)."""
     if N is None:
-        N = nonlinear_rot(prob, u)
+        N = nonlinear_term(prob, u)
     out = predictor_corrector(prob, N, N_prev, u, u_prev, detail=detail)
     if detail:
         return out[0], out[1], N, out[2]
@@ -131,7 +133,7 @@ def run(prob, u0, nsteps, u_prev=None, N_prev=None):
     """nsteps steps from u0 (history defaults to u^{-1} = u^0, N^{-1} = N(u^0))."""
     u = u0.copy()
     up = u.copy() if u_prev is None else u_prev.copy()
-    Np = nonlinear_rot(prob, up) if N_prev is None else N_prev.copy()
+    Np = nonlinear_term(prob, up) if N_prev is None else N_prev.copy()
     p = None
     for _ in range(nsteps):
         un, p, N = step(prob, u, up, Np)

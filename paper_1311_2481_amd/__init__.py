@@ -22,6 +22,7 @@ TC_OK, TC_EINVAL, TC_ENOMEM, TC_ESINGULAR, TC_EHIP, TC_ENONFINITE = range(6)
 STATUS_NAMES = {0: "TC_OK", 1: "TC_EINVAL", 2: "TC_ENOMEM", 3: "TC_ESINGULAR", 4: "TC_EHIP", 5: "TC_ENONFINITE"}
 SOLVE_KINDS = {"P": 0, "Up": 1, "Um": 2, "Uz": 3, "Phi": 4}
 PRECISIONS = {"fp64": 0, "fp32_bulk": 1}
+FORMS = {"rot": 0, "conv": 1}
 KERNELS = {"pc": 0, "curl": 1, "zinv": 2, "theta": 3, "zfwd": 4}
 
 
@@ -35,13 +36,14 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n_r", ctypes.c_int32), ("m_theta", ctypes.c_int32), ("m_z", ctypes.c_int32),
                 ("p_theta", ctypes.c_int32), ("p_z", ctypes.c_int32), ("k_theta", ctypes.c_double),
                 ("k_z", ctypes.c_double), ("alpha", ctypes.c_double), ("n_s", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("form", ctypes.c_int32)]
 
 
 _lib = None
 EXPORTS = ["tc_init", "tc_destroy", "tc_last_error", "tc_radial_nodes", "tc_set_state", "tc_get_state",
            "tc_get_history", "tc_step", "tc_nonlinear", "tc_helmholtz_solve", "tc_helmholtz_solve_transposed",
-           "tc_step_adjoint", "tc_perturbation_energy_gradient", "tc_get_diag", "tc_get_diag_noalloc", "tc_check_finite", "tc_set_timing", "tc_kernel_time",
+           "tc_step_adjoint", "tc_perturbation_energy_gradient", "tc_adjoint_seed", "tc_adjoint_initial_history",
+           "tc_control_velocity", "tc_control_gradient", "tc_control_ascent_update", "tc_get_diag", "tc_get_diag_noalloc", "tc_check_finite", "tc_set_timing", "tc_kernel_time", "tc_factor_backward_error",
            "tc_memory_bytes"]
 
 
@@ -68,12 +70,18 @@ def load_library(path=LIB_PATH):
     lib.tc_helmholtz_solve_transposed.argtypes = [vp, i32, vp, vp]
     lib.tc_step_adjoint.argtypes = [vp, vp, vp, vp]
     lib.tc_perturbation_energy_gradient.argtypes = [vp, vp, vp]
+    lib.tc_adjoint_seed.argtypes = [vp, vp, dbl, vp]
+    lib.tc_adjoint_initial_history.argtypes = [vp, vp, vp, vp]
+    lib.tc_control_velocity.argtypes = [vp, vp, vp]
+    lib.tc_control_gradient.argtypes = [vp, vp, vp]
+    lib.tc_control_ascent_update.argtypes = [vp, vp, vp, vp, dbl, dbl, vp, ctypes.POINTER(dbl)]
     lib.tc_get_diag.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.tc_get_diag_noalloc.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.tc_check_finite.argtypes = [vp]
     lib.tc_set_timing.argtypes = [vp, i32]
     lib.tc_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i32)]
     lib.tc_memory_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.tc_factor_backward_error.argtypes = [vp, ctypes.POINTER(dbl)]
     for name in EXPORTS:
         if name != "tc_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -85,7 +93,7 @@ class Solver:
     """One Taylor-Couette configuration on one GPU (wraps a tc_ctx)."""
 
     def __init__(self, n_r, m_theta, m_z, eta, Re_i, Re_o, dt, k_theta=1.0, k_z=1.0, alpha=0.0,
-                 precision="fp64", p_theta=0, p_z=0, device="cuda"):
+                 precision="fp64", p_theta=0, p_z=0, device="cuda", form="rot"):
         self.lib = load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
@@ -96,8 +104,9 @@ class Solver:
         self.eta, self.Re_i, self.Re_o, self.dt = float(eta), float(Re_i), float(Re_o), float(dt)
         self.k_theta, self.k_z, self.alpha = float(k_theta), float(k_z), float(alpha)
         self.precision = precision
+        self.form = form
         g = _Grid(self.n_r, self.m_theta, self.m_z, int(p_theta), int(p_z), self.k_theta, self.k_z, self.alpha, 9,
-                  PRECISIONS[precision])
+                  PRECISIONS[precision], FORMS[form])
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             ctx = ctypes.c_void_p()
@@ -177,6 +186,58 @@ class Solver:
         g = self.empty(3) if out is None else out
         self._check(self.lib.tc_perturbation_energy_gradient(self.ctx, self._arr(u, 3, "u"), self._arr(g, 3, "g")))
         return g
+
+    def adjoint_seed(self, uT, scale=1.0, out=None):
+        g = self.empty(3) if out is None else out
+        self._check(self.lib.tc_adjoint_seed(self.ctx, self._arr(uT, 3, "uT"), float(scale), self._arr(g, 3, "g")))
+        return g
+
+    def adjoint_initial_history(self, u0, adj_in, out=None):
+        g = self.empty(3) if out is None else out
+        self._check(self.lib.tc_adjoint_initial_history(self.ctx, self._arr(u0, 3, "u0"),
+                                                        self._arr(adj_in, 9, "adj_in"), self._arr(g, 3, "g")))
+        return g
+
+    # -------------------------------------------------------------- optimal-perturbation control
+    @property
+    def control_shape(self):
+        return (3, 4, self.m_z, self.m_theta)
+
+    def _ctl(self, t, name):
+        if t is None:
+            return None
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.device != self.device
+                or not t.is_contiguous() or tuple(t.shape) != self.control_shape):
+            raise ValueError(f"{name} must be a contiguous complex128 tensor of shape {self.control_shape} "
+                             f"on {self.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def control_zeros(self):
+        return torch.zeros(self.control_shape, dtype=torch.complex128, device=self.device)
+
+    def control_velocity(self, a, out=None):
+        u = self.empty(3) if out is None else out
+        self._check(self.lib.tc_control_velocity(self.ctx, self._ctl(a, "a"), self._arr(u, 3, "u")))
+        return u
+
+    def control_gradient(self, g, out=None):
+        ga = self.control_zeros() if out is None else out
+        self._check(self.lib.tc_control_gradient(self.ctx, self._arr(g, 3, "g"), self._ctl(ga, "ga")))
+        return ga
+
+    def control_ascent_update(self, a, gJ, gE, tau, E0, out=None):
+        res = self.control_zeros() if out is None else out
+        st = np.zeros(5)
+        self._check(self.lib.tc_control_ascent_update(self.ctx, self._ctl(a, "a"), self._ctl(gJ, "gJ"),
+                                                      self._ctl(gE, "gE"), float(tau), float(E0),
+                                                      self._ctl(res, "a_out"),
+                                                      st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return res, dict(beta=st[0], energy_before=st[1], scale=st[2], step_norm=st[3], control_norm=st[4])
+
+    def factor_backward_error(self):
+        err = ctypes.c_double()
+        self._check(self.lib.tc_factor_backward_error(self.ctx, ctypes.byref(err)))
+        return err.value
 
     def diag(self):
         out = np.zeros(8)

@@ -37,8 +37,7 @@ class TCSteps(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         S = ctx.solver
-        scale = float(gJ)
-        ub = S.energy_gradient(ctx.uT) * scale
+        ub = S.adjoint_seed(ctx.uT, float(gJ))
         upb = torch.zeros_like(ub)
         Nb = torch.zeros_like(ub)
         adj_in = S.empty(9)
@@ -57,11 +56,8 @@ class TCSteps(torch.autograd.Function):
                 out = S.step_adjoint(fwd, adj_in)
                 ub, upb, Nb = out[0:3], out[3:6], out[6:9]
         # initial history: u^{-1} = u^0 and N^{-1} = N(u^0)
-        zero = torch.zeros_like(ub)
-        adj_in[0:3], adj_in[3:6], adj_in[6:9] = zero, zero, Nb
-        fwd = torch.cat([ctx.u0, ctx.u0], 0)
-        nl = S.step_adjoint(fwd, adj_in)[0:3]
-        g = ub + upb + nl
+        adj_in[0:3], adj_in[3:6], adj_in[6:9] = ub, upb, Nb
+        g = S.adjoint_initial_history(ctx.u0, adj_in)
         return g, None, None, None, None
 
 

@@ -8,6 +8,8 @@
 // transpose: transposed banded solves, D1^T stencils, conjugated i*b
 // factors.  Reverse order of the forward chain:
 //   u^{i+1} = u* - grad phi          -> phi_bar = -grad^H u_bar', u*_bar = u_bar'
+//     (mode (0,0): u^{i+1}+- = u*+- - u*_r, so phi_bar = 0 there and
+//     u*_bar+- = (u_bar'+- - u_bar'-+)/2)
 //   phi = P^-1 div(u*) (interior)    -> r_bar = P^-T phi_bar, u*_bar += div^H(r_bar)
 //   u* = H^-1 rhs_u                  -> rhs_u_bar = H^-T u*_bar (interior rows)
 //   rhs_u = -(4u - u_prev)/(2dt) + Ne + grad p*
@@ -102,7 +104,8 @@ __global__ void k_adj_phi(const double* __restrict__ rc, Dims d, const cd* __res
   if (!make_slot(d, q)) return;
   const int k = q.k;
   const int64_t o = k * d.S + q.idx;
-  if (q.nyq) {
+  // mode (0,0) takes no gradient of phi (its correction is -u*_r instead)
+  if (q.nyq || q.zero_mode) {
     out[o] = cz();
     return;
   }
@@ -130,8 +133,15 @@ __global__ void k_adj_ustar(const double* __restrict__ rc, Dims d, const cd* __r
   const double ir = rc[(int64_t)k * RC_N + RC_IR];
   const cd f = mr(k);
   const cd dt = cs(gather_t(rc, d, k, RC_W1, mr), 0.5);
-  us[o] = cpl(ub[o], cpl(dt, cs(f, 0.5 * (1.0 + q.a) * ir)));
-  us[d.F + o] = cpl(ub[d.F + o], cpl(dt, cs(f, 0.5 * (1.0 - q.a) * ir)));
+  // mode (0,0): u^{i+1}+- = u*+- - u*_r, whose transpose maps (v+, v-) to
+  // ((v+ - v-)/2, (v- - v+)/2)
+  cd vp = ub[o], vm = ub[d.F + o];
+  if (q.zero_mode) {
+    vp = cs(cmi(ub[o], ub[d.F + o]), 0.5);
+    vm = cd{-vp.x, -vp.y};
+  }
+  us[o] = cpl(vp, cpl(dt, cs(f, 0.5 * (1.0 + q.a) * ir)));
+  us[d.F + o] = cpl(vm, cpl(dt, cs(f, 0.5 * (1.0 - q.a) * ir)));
   us[2 * d.F + o] = cmi(ub[2 * d.F + o], cimul(f, q.b));
 }
 
@@ -258,9 +268,71 @@ __global__ void k_adj_curl(const double* __restrict__ rc, Dims d, const cd* __re
 
 using namespace tc;
 
+namespace {
+
+// Work space of the adjoint calls: 13 fields + the 9-field transform
+// buffer (double), allocated on first use.
+tc_status ensure_aux(tc_ctx* c) {
+  const Dims& d = c->d;
+  const size_t FB = (size_t)d.F * sizeof(cd);
+  const size_t inter9 = (size_t)9 * d.pz * d.mt * sizeof(cd) * d.n_r;
+  const size_t need = 13 * FB + inter9;
+  if (c->aux_bytes >= need) return TC_OK;
+  if (c->aux) {
+    (void)hipFree(c->aux);
+    c->bytes -= c->aux_bytes;
+    c->aux = nullptr;
+    c->aux_bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, TC_ENOMEM, "cannot allocate the adjoint work space");
+  }
+  c->aux = static_cast<cd*>(p);
+  c->aux_bytes = need;
+  c->bytes += need;
+  return TC_OK;
+}
+
+// Transposed nonlinear term: out += N'(u)^T nbar + keep (3 fields each);
+// nl6 (6 fields) and inter (9-field transform buffer) are work space.
+hipError_t adjoint_nonlinear(tc_ctx* c, const cd* u, const cd* nbar, const cd* keep, cd* out, cd* nl6, void* inter) {
+  const Dims& d = c->d;
+  const int64_t F = d.F;
+  c->omega_fresh = false;  // the context's curl buffer now holds curl(u)
+  hipError_t e = launch_curl(c, u, c->omega);
+  if (e != hipSuccess) return e;
+  ZIo zi{};
+  for (int k = 0; k < 3; ++k) {
+    zi.src[k] = u + k * F;
+    zi.src[3 + k] = c->omega + k * F;
+    zi.src[6 + k] = nbar + k * F;
+  }
+  zi.nfields = 9;
+  zi.nf_plane = 9;
+  ZIo zo{};
+  for (int k = 0; k < 6; ++k) zo.dst[k] = nl6 + k * F;
+  zo.nfields = 6;
+  zo.nf_plane = 9;
+  // the transpose of the forward transform carries its 1/(P_theta P_z)
+  zo.scale = 1.0 / ((double)d.pt * (double)d.pz);
+  zo.weights = 1;
+  e = launch_zinv_io(c, 0, d.n_r, zi, inter, false);
+  if (e == hipSuccess) e = launch_theta_adj(c, d.n_r, inter);
+  if (e == hipSuccess) e = launch_zfwd_io(c, 0, d.n_r, zo, inter, false);
+  if (e != hipSuccess) return e;
+  const dim3 blk(SLOT_BLOCK), grd((unsigned)(8 * ((slot_tiles(d) + 7) / 8)));
+  hipLaunchKernelGGL(k_adj_curl, grd, blk, 0, c->stream, c->rc_dev, d, nl6, keep, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj_in, void* adj_out) {
   if (!c) return TC_EINVAL;
   if (!fwd || !adj_in || !adj_out) return fail(c, TC_EINVAL, "NULL array");
+  if (c->d.form != TC_ROTATIONAL) return fail(c, TC_EINVAL, "the adjoint step is built for the rotational form");
   const Dims& d = c->d;
   const int64_t F = d.F;
   const size_t FB = (size_t)F * sizeof(cd);
@@ -269,26 +341,8 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
     const char* b = static_cast<const char*>(adj_out);
     if (a < b + 9 * FB && b < a + 9 * FB) return fail(c, TC_EINVAL, "adj_in and adj_out overlap");
   }
-  // work space: 13 fields + the 9-field transform buffer (double)
   const int NW = 13;
-  const size_t inter9 = (size_t)9 * d.pz * d.mt * sizeof(cd) * d.n_r;
-  const size_t need = NW * FB + inter9;
-  if (c->aux_bytes < need) {
-    if (c->aux) {
-      (void)hipFree(c->aux);
-      c->bytes -= c->aux_bytes;
-      c->aux = nullptr;
-      c->aux_bytes = 0;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, need) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c, TC_ENOMEM, "cannot allocate the adjoint work space");
-    }
-    c->aux = static_cast<cd*>(p);
-    c->aux_bytes = need;
-    c->bytes += need;
-  }
+  if (tc_status sa = ensure_aux(c); sa != TC_OK) return sa;
   cd* w = c->aux;
   cd* phib = w + 0 * F;
   cd* rphi = w + 1 * F;
@@ -331,28 +385,29 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, ru, out_u, out_up, nin, out_np, ntot);
   TC_TRY(hipGetLastError());
   // nonlinear term, transposed: forward fields u, omega(u) and the cotangent N_tot
-  c->omega_fresh = false;  // the context's curl buffer now holds curl(fwd u)
-  TC_TRY(launch_curl(c, u, c->omega));
-  ZIo zi{};
-  for (int k = 0; k < 3; ++k) {
-    zi.src[k] = u + k * F;
-    zi.src[3 + k] = c->omega + k * F;
-    zi.src[6 + k] = ntot + k * F;
-  }
-  zi.nfields = 9;
-  zi.nf_plane = 9;
-  ZIo zo{};
-  for (int k = 0; k < 6; ++k) zo.dst[k] = nl6 + k * F;
-  zo.nfields = 6;
-  zo.nf_plane = 9;
-  // the transpose of the forward transform carries its 1/(P_theta P_z)
-  zo.scale = 1.0 / ((double)d.pt * (double)d.pz);
-  zo.weights = 1;
-  TC_TRY(launch_zinv_io(c, 0, d.n_r, zi, inter, false));
-  TC_TRY(launch_theta_adj(c, d.n_r, inter));
-  TC_TRY(launch_zfwd_io(c, 0, d.n_r, zo, inter, false));
-  hipLaunchKernelGGL(k_adj_curl, grd, blk, 0, st, c->rc_dev, d, nl6, ukeep, out_u);
-  TC_TRY(hipGetLastError());
+  TC_TRY(adjoint_nonlinear(c, u, ntot, ukeep, out_u, nl6, inter));
 #undef TC_TRY
   return TC_OK;
+}
+
+// Start of the reverse sweep at step 0, whose history is u^{-1} = u^0 and
+// N^{-1} = N(u^0): g = u_bar + u_prev_bar + N'(u^0)^T N_bar.
+extern "C" tc_status tc_adjoint_initial_history(tc_ctx* c, const void* u0, const void* adj_in, void* g) {
+  if (!c) return TC_EINVAL;
+  if (!u0 || !adj_in || !g) return fail(c, TC_EINVAL, "NULL array");
+  if (c->d.form != TC_ROTATIONAL) return fail(c, TC_EINVAL, "the adjoint step is built for the rotational form");
+  const int64_t F = c->d.F;
+  const size_t FB = (size_t)F * sizeof(cd);
+  {
+    const char* a = static_cast<const char*>(adj_in);
+    const char* b = static_cast<const char*>(g);
+    if (a < b + 3 * FB && b < a + 9 * FB) return fail(c, TC_EINVAL, "adj_in and g overlap");
+  }
+  if (tc_status sa = ensure_aux(c); sa != TC_OK) return sa;
+  const cd* ub = static_cast<const cd*>(adj_in);
+  cd* out = static_cast<cd*>(g);
+  hipError_t e = hipMemcpyAsync(out, ub, 3 * FB, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = adjoint_nonlinear(c, static_cast<const cd*>(u0), ub + 6 * F, ub + 3 * F, out, c->aux + 2 * F, c->aux + 13 * F);
+  return hip_check(c, e, "tc_adjoint_initial_history");
 }

@@ -141,15 +141,44 @@ void twiddles(int L, std::vector<C2<T>>& out) {
 void free_ctx(tc_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->rc_dev, c->fac, c->tw_t, c->tw_z, c->twf_t, c->twf_z, c->u, c->u_prev, c->N_prev,
-                  c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax, c->diag_wr, c->diag_uc};
+                  c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax, c->diag_wr, c->diag_uc, c->red};
   for (void* p : ptrs) dev_free(p);
   for (auto& t : c->timers)
     for (auto e : t.ev) (void)hipEventDestroy(e);
   delete c;
 }
 
+// One evaluation of the nonlinear term in the convective form: the radial
+// derivatives of u, then per plane batch the axial, azimuthal and forward
+// axial passes over the 9-field intermediate.
+tc_status nonlinear_conv(tc_ctx* c, const cd* u, cd* N) {
+  hipError_t e = hipSuccess;
+  c->omega_fresh = false;  // the curl buffer holds D1 u here
+  timer_begin(c, TK_CURL);
+  e = launch_dr(c, u, c->omega);
+  timer_end(c, TK_CURL);
+  if (e != hipSuccess) return hip_check(c, e, "radial derivatives");
+  for (int p0 = 0; p0 < c->d.n_r; p0 += c->batch) {
+    const int np = std::min(c->batch, c->d.n_r - p0);
+    timer_begin(c, TK_ZINV);
+    e = launch_zinv_conv(c, p0, np, u, c->omega);
+    timer_end(c, TK_ZINV);
+    if (e != hipSuccess) return hip_check(c, e, "axial inverse transform");
+    timer_begin(c, TK_THETA);
+    e = launch_theta_conv(c, p0, np);
+    timer_end(c, TK_THETA);
+    if (e != hipSuccess) return hip_check(c, e, "azimuthal transforms");
+    timer_begin(c, TK_ZFWD);
+    e = launch_zfwd(c, p0, np, N);
+    timer_end(c, TK_ZFWD);
+    if (e != hipSuccess) return hip_check(c, e, "axial forward transform");
+  }
+  return TC_OK;
+}
+
 // One evaluation of the nonlinear term: u -> N (both 3 fields).
 tc_status nonlinear(tc_ctx* c, const cd* u, cd* N) {
+  if (c->d.form == TC_CONVECTIVE) return nonlinear_conv(c, u, N);
   hipError_t e = hipSuccess;
   // the previous step's last sweep may already have formed curl(u)
   if (!(u == c->u && c->omega_fresh)) {
@@ -321,6 +350,7 @@ __global__ void k_slip(Dims d, const cd* __restrict__ u, double* __restrict__ pa
 // g_z = A w_j r_j c_n u_z, A = (2 pi / k_theta)(2 pi / k_z).
 __global__ void k_egrad(const double* __restrict__ rc, Dims d, double C1, double C2, double area,
                         const cd* __restrict__ u, cd* __restrict__ g) {
+  // (area carries the seed's scale factor)
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.S) return;
   const int s = (int)(idx / d.mt), n = (int)(idx - (int64_t)s * d.mt);
@@ -357,6 +387,7 @@ __global__ void k_finite(int64_t count, const double* __restrict__ x, int* __res
 }
 
 }  // namespace tc
+
 
 namespace {
 
@@ -485,6 +516,24 @@ double* diag_scratch(const tc_ctx* c) {
 
 }  // namespace
 
+namespace tc {
+
+hipError_t energy_of(tc_ctx* c, const cd* u, double& E) {
+  const int nb = 1024;
+  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->stream, c->d, u, c->diag_wr, c->diag_uc, 0, c->red);
+  hipError_t e = hipGetLastError();
+  std::vector<double> h(nb, 0.0);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), c->red, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  double sum = 0.0;
+  for (int i = 0; i < nb; ++i) sum += h[i];
+  const double area = (2.0 * M_PI / c->d.kt) * (2.0 * M_PI / c->d.kz);
+  E = 0.5 * area * sum;
+  return e;
+}
+
+}  // namespace tc
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -523,6 +572,8 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   else if (G.m_theta < 1 || G.m_z < 2 || (G.m_z % 2)) why = "m_theta >= 1 and even m_z >= 2 required";
   else if (G.n_s != 9) why = "only n_s = 9 is supported";
   else if (G.precision != TC_FP64 && G.precision != TC_FP32_BULK) why = "unknown precision";
+  else if (G.form != TC_ROTATIONAL && G.form != TC_CONVECTIVE) why = "unknown form of the nonlinear term";
+  else if (G.form == TC_CONVECTIVE && G.precision != TC_FP64) why = "the convective form runs in FP64 only";
   else if (G.p_theta < 3 * G.m_theta - 2 || G.p_z < 3 * G.m_z / 2 - 2) why = "dealiased grid below the 3/2 rule";
   else if (!fft_length_supported(G.p_theta) || !fft_length_supported(G.p_z)) why = "unsupported transform length";
   else if (!(eta > 0.0 && eta < 1.0)) why = "eta must be in (0, 1)";
@@ -561,6 +612,7 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   d.dt = dt;
   d.Re_i = Re_i;
   d.Re_o = Re_o;
+  d.form = G.form;
 
   // radial grid and per-node constants
   c->r = radial_nodes(d.n_r, eta, G.alpha);
@@ -605,6 +657,7 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   c->zmax = dev_alloc<unsigned int>(c, (size_t)ZMAX_WORDS * d.n_r * sizeof(unsigned int), st);
   c->diag_wr = dev_alloc<double>(c, (size_t)d.n_r * sizeof(double), st);
   c->diag_uc = dev_alloc<double>(c, (size_t)d.n_r * sizeof(double), st);
+  c->red = dev_alloc<double>(c, TC_RED_DOUBLES * sizeof(double), st);
   // plane batch of the nonlinear term: all planes when they fit a budget
   {
     const size_t per = inter_bytes_per_plane(c);
@@ -677,6 +730,38 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
     g_init_error = "zero or non-finite pivot in the banded factorisation";
     free_ctx(c);
     return TC_ESINGULAR;
+  }
+  // the factors are unpivoted: check their backward error on one solve per
+  // operator and mode before accepting them
+  {
+    double* tmp = nullptr;
+    unsigned long long* worst = nullptr;
+    unsigned long long hw = 0;
+    const size_t tb = (size_t)d.n_r * NOPS * d.ndm * sizeof(double);
+    if (hipMalloc(&tmp, tb) != hipSuccess || hipMalloc(&worst, sizeof(*worst)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (tmp) (void)hipFree(tmp);
+      g_init_error = "hipMalloc of the factor check's work space failed";
+      free_ctx(c);
+      return TC_ENOMEM;
+    }
+    e = hipMemsetAsync(worst, 0, sizeof(*worst), c->stream);
+    if (e == hipSuccess) e = launch_factor_check(c, tmp, worst);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hw, worst, sizeof(hw), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    (void)hipFree(worst);
+    if (e != hipSuccess) {
+      g_init_error = std::string("HIP error during the factor check: ") + hipGetErrorString(e);
+      free_ctx(c);
+      return TC_EHIP;
+    }
+    std::memcpy(&c->factor_error, &hw, sizeof(double));
+    if (!(c->factor_error <= TC_FACTOR_CHECK_MAX)) {
+      g_init_error = "the unpivoted factors fail the backward-error check (" + std::to_string(c->factor_error) + ")";
+      free_ctx(c);
+      return TC_ESINGULAR;
+    }
   }
   // the allocation-free diagnostics' scratch address on this device
   if (hipGetDevice(&c->device) != hipSuccess || !scratch_address(c->device)) {
@@ -840,6 +925,19 @@ tc_status tc_get_diag_noalloc(tc_ctx* c, double* out) {
   return TC_OK;
 }
 
+tc_status tc_adjoint_seed(tc_ctx* c, const void* u, double scale, void* g) {
+  if (!c) return TC_EINVAL;
+  if (!u || !g) return fail(c, TC_EINVAL, "NULL array");
+  if (!std::isfinite(scale)) return fail(c, TC_EINVAL, "scale must be finite");
+  const Dims& d = c->d;
+  const double C1 = (d.Re_o - c->eta * d.Re_i) / (1.0 + c->eta);
+  const double C2 = c->eta * (d.Re_i - c->eta * d.Re_o) / ((1.0 - c->eta) * (1.0 - c->eta * c->eta));
+  const double area = scale * (2.0 * M_PI / d.kt) * (2.0 * M_PI / d.kz);
+  hipLaunchKernelGGL(k_egrad, dim3((unsigned)((d.S + 255) / 256)), dim3(256), 0, c->stream, c->rc_dev, d, C1, C2,
+                     area, static_cast<const cd*>(u), static_cast<cd*>(g));
+  return hip_check(c, hipGetLastError(), "tc_adjoint_seed");
+}
+
 tc_status tc_perturbation_energy_gradient(tc_ctx* c, const void* u, void* g) {
   if (!c) return TC_EINVAL;
   if (!u || !g) return fail(c, TC_EINVAL, "NULL array");
@@ -893,6 +991,12 @@ tc_status tc_kernel_time(tc_ctx* c, int32_t which, double* ms_out, int32_t* laun
   }
   *ms_out = n ? tot / n : 0.0;
   if (launches_out) *launches_out = n;
+  return TC_OK;
+}
+
+tc_status tc_factor_backward_error(const tc_ctx* c, double* out) {
+  if (!c || !out) return TC_EINVAL;
+  *out = c->factor_error;
   return TC_OK;
 }
 

@@ -36,6 +36,9 @@ enum { OP_P = 0, OP_HP = 1, OP_HM = 2, OP_HZ = 3 };
 // Doubles of the static scratch array of tc_get_diag_noalloc (4 MiB per GPU).
 constexpr size_t TC_DIAG_SCRATCH_DOUBLES = (size_t)1 << 19;
 
+// Doubles of the context's reduction buffer (block partials).
+constexpr size_t TC_RED_DOUBLES = 4096;
+
 // Launch timing slots (tc_kernel_time).
 enum { TK_PC = 0, TK_CURL = 1, TK_ZINV = 2, TK_THETA = 3, TK_ZFWD = 4, TK_N = 5 };
 
@@ -61,6 +64,7 @@ struct ZIo {
   double scale;
   unsigned int* zmax;
   int zmax_slot[9];
+  int mulb[9];  // inverse kernel: input field k is multiplied by i l k_z (its z derivative) when set
 };
 
 struct Dims {
@@ -69,6 +73,7 @@ struct Dims {
   int64_t F;      // n_r * S (one field)
   double kt, kz, dt, Re_i, Re_o;
   double s0, sM;  // scale of the Neumann rows of P (rows 0 and M)
+  int form;       // tc_form of the nonlinear term
 };
 
 }  // namespace tc
@@ -100,7 +105,9 @@ struct tc_ctx {
   unsigned int* zmax = nullptr;  // per-plane field magnitudes (ZMAX_WORDS n_r words)
   double* diag_wr = nullptr;     // trapezoid weight times r on every node
   double* diag_uc = nullptr;     // circular Couette u_theta on every node
+  double* red = nullptr;         // block partials of small reductions (TC_RED_DOUBLES)
   int device = -1;               // HIP device the context was created on
+  double factor_error = 0.0;     // backward error of the factor check at tc_init
   int batch = 0;
   size_t bytes = 0;
   int64_t steps = 0;
@@ -118,6 +125,11 @@ tc_status hip_check(tc_ctx* c, hipError_t e, const char* what);
 
 // launchers (return hipError_t from hipGetLastError)
 hipError_t launch_factor(tc_ctx* c, int* bad_dev);
+// componentwise backward error of the stored factors on one solve per
+// operator and mode (tmp: n_r * 4 * ndm doubles of work space)
+hipError_t launch_factor_check(tc_ctx* c, double* tmp, unsigned long long* worst_dev);
+// largest backward error tc_init accepts from that check
+constexpr double TC_FACTOR_CHECK_MAX = 1e-12;
 hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x);
 // transposed solves of nop (1, or 3 starting at OP_HP) operators on
 // consecutive fields rhs + k F -> x + k F (x may alias rhs)
@@ -134,8 +146,17 @@ hipError_t launch_zfwd(tc_ctx* c, int plane0, int nplanes, cd* N);
 hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, bool f32);
 hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32);
 hipError_t launch_theta_adj(tc_ctx* c, int nplanes, void* inter);
+// convective form: radial derivatives D1 u (3 fields) and the azimuthal
+// pass over the 9-field intermediate of planes plane0 ..
+hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du);
+hipError_t launch_zinv_conv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* du);
+hipError_t launch_theta_conv(tc_ctx* c, int plane0, int nplanes);
+int inter_fields(const tc_ctx* c);
 bool fft_length_supported(int L);
 size_t inter_bytes_per_plane(const tc_ctx* c);
+
+// kinetic energy 1/2 int |u|^2 dV of a velocity (synchronous; uses ctx->red)
+hipError_t energy_of(tc_ctx* c, const cd* u, double& E);
 
 // timing helpers (no-ops unless ctx->timing)
 void timer_begin(tc_ctx* c, int which);

@@ -33,6 +33,9 @@
 namespace tc {
 
 // ------------------------------------------------------------------ curl
+// KIND 0: omega = curl u; KIND 1: the radial derivatives D1 u+, D1 u-, D1 u_z
+// that the convective form transforms.
+template <int KIND>
 __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dims d, const cd* __restrict__ u,
                                               cd* __restrict__ w) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,6 +75,13 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dim
       dmn.x = fma(c, wm[k].x, dmn.x); dmn.y = fma(c, wm[k].y, dmn.y);
       dz.x = fma(c, wz[k].x, dz.x); dz.y = fma(c, wz[k].y, dz.y);
     }
+    const int64_t o = i * S + idx;
+    if constexpr (KIND == 1) {
+      w[o] = dp;
+      w[F + o] = dmn;
+      w[2 * F + o] = dz;
+      continue;
+    }
     const cd up = wp[HW], um = wm[HW], uz = wz[HW];
     // omega+ = i (a/r uz - D1 uz) - b u+ ;  omega- = i (a/r uz + D1 uz) + b u-
     const cd tp = {a * ir * uz.x - dz.x, a * ir * uz.y - dz.y};
@@ -82,7 +92,6 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dim
     const cd q = {dp.x + (1.0 + a) * ir * up.x - dmn.x - (1.0 - a) * ir * um.x,
                   dp.y + (1.0 + a) * ir * up.y - dmn.y - (1.0 - a) * ir * um.y};
     const cd oz = {0.5 * q.y, -0.5 * q.x};
-    const int64_t o = i * S + idx;
     w[o] = op;
     w[F + o] = om;
     w[2 * F + o] = oz;
@@ -93,6 +102,7 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ rc, Dim
 // slots, y over nodes): each thread applies row k of D1 to the 9 rows
 // around it.  For small grids, where the marching kernel has too few lanes
 // to hide memory latency; the rows it re-reads are then cache resident.
+template <int KIND>
 __global__ __launch_bounds__(256) void k_curl_points(const double* __restrict__ rc, Dims d, const cd* __restrict__ u,
                                                      cd* __restrict__ w) {
   const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,6 +134,12 @@ __global__ __launch_bounds__(256) void k_curl_points(const double* __restrict__ 
     dmn.x = fma(c, m.x, dmn.x); dmn.y = fma(c, m.y, dmn.y);
     dz.x = fma(c, z.x, dz.x); dz.y = fma(c, z.y, dz.y);
   }
+  if constexpr (KIND == 1) {
+    w[o] = dp;
+    w[F + o] = dmn;
+    w[2 * F + o] = dz;
+    return;
+  }
   const cd up = u[o], um = u[F + o], uz = u[2 * F + o];
   // omega+ = i (a/r uz - D1 uz) - b u+ ;  omega- = i (a/r uz + D1 uz) + b u-
   const cd tp = {a * ir * uz.x - dz.x, a * ir * uz.y - dz.y};
@@ -142,17 +158,22 @@ __global__ void k_clear_words(unsigned int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) {
+template <int KIND>
+static hipError_t run_curl(tc_ctx* c, const cd* u, cd* out) {
   const int64_t blocks = (c->d.S + 255) / 256;
   // marching lanes (one per slot) fill fewer than 2 waves per SIMD below
   // 131072 slots per plane: use one thread per point instead
   if (c->d.S < 131072)
-    hipLaunchKernelGGL(k_curl_points, dim3((unsigned)blocks, (unsigned)c->d.n_r), dim3(256), 0, c->stream, c->rc_dev,
-                       c->d, u, omega);
+    hipLaunchKernelGGL(k_curl_points<KIND>, dim3((unsigned)blocks, (unsigned)c->d.n_r), dim3(256), 0, c->stream,
+                       c->rc_dev, c->d, u, out);
   else
-    hipLaunchKernelGGL(k_curl, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, omega);
+    hipLaunchKernelGGL(k_curl<KIND>, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->rc_dev, c->d, u, out);
   return hipGetLastError();
 }
+
+hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega) { return run_curl<0>(c, u, omega); }
+
+hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du) { return run_curl<1>(c, u, du); }
 
 // Scaled packing of u_z and omega_z in the float azimuthal transforms.
 #ifndef TC_F32_ZSCALE
@@ -290,6 +311,10 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
         if (e < h) sl = e;
         else if (e > L - h) sl = d.mz - (L - e);
         raw[k][q] = (sl >= 0 && n < d.mt && FI::in_valid(t, k)) ? src[(int64_t)sl * d.mt] : cd{0.0, 0.0};
+        if (io.mulb[fld]) {  // i b v, b = l k_z: the axial derivative
+          const double bb = (double)(sl < h ? sl : sl - d.mz) * d.kz;
+          raw[k][q] = cd{-bb * raw[k][q].y, bb * raw[k][q].x};
+        }
       }
   };
   auto transform_store = [&](int id, cd (&raw)[FI::PER0][FI::R0]) {
@@ -482,6 +507,180 @@ void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter, const C2<T>* __rest
   FF::template run<RPB>(nz, o, bufa, bufb, W, t, f);
   if (valid) {
     C2<T>* Bz = base + 2 * fstride;
+#pragma unroll
+    for (int k = 0; k < FF::PERN; ++k)
+      if (FF::out_valid(t, k))
+#pragma unroll
+        for (int s2 = 0; s2 < FF::RN; ++s2) {
+          const int e = FF::out_index(t, k, s2);
+          if (e < mt) Bz[e] = o[k][s2];
+        }
+  }
+}
+
+// ------------------------------------------------------------------ theta pass, convective form
+// The paper's form N = u.grad u (Sec. 3.2, step 1) with the curvature terms
+// of eq. NS_cyl, per z-row of a 9-field intermediate: u+, u-, u_z, their
+// radial derivatives D1 u+-, D1 u_z, and their axial derivatives i b u+-,
+// i b u_z (formed in the axial pass).  Six complex theta transforms carry
+// the twelve real fields:
+//   h_u = u_r + i u_theta                  spectrum (u+, u-) as a +- pair
+//   h_r = d_r u_r + i d_r u_theta          (D1 u+, D1 u-)
+//   h_t = (d_theta u_r + i d_theta u_theta)/r   = (i n k_theta / r) times h_u's
+//   h_z = d_z u_r + i d_z u_theta          (i b u+, i b u-)
+//   g1  = u_z + i d_r u_z,   g2 = d_theta u_z / r + i d_z u_z
+// and in physical space, with real u_r, u_theta, u_z,
+//   N_r + i N_theta = u_r h_r + u_theta h_t + u_z h_z + i (u_theta / r) h_u
+//   (the curvature terms -u_theta^2/r and +u_theta u_r/r), and
+//   N_z = u_r d_r u_z + u_theta d_theta u_z / r + u_z d_z u_z.
+// The products are accumulated as each inverse transform completes, so at
+// most h_u, u_z and the two accumulators are held.  Outputs overwrite
+// fields 0-2 of the row, as in the rotational kernel.
+template <int L>
+__global__ __launch_bounds__((TShape<double, L>::TPF * TShape<double, L>::RPB))
+#if TC_THETA_WAVES
+__attribute__((amdgpu_waves_per_eu(L >= 1024 ? TC_THETA_WAVES : 1)))
+#endif
+void k_theta_conv(Dims d, int plane0, int nplanes, cd* __restrict__ inter, const cd* __restrict__ W,
+                  const double* __restrict__ rc) {
+  using T = double;
+  using TS = TShape<T, L>;
+  constexpr int TPF = TS::TPF, RPB = TS::RPB;
+  using FI = Fft<T, L, TPF, +1, TS::FIREV>;
+  using FF = Fft<T, L, TPF, -1, !TS::FIREV>;
+  static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
+  extern __shared__ unsigned char lds_raw[];
+  cd* bufa = reinterpret_cast<cd*>(lds_raw);
+  cd* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
+  const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
+  const int64_t rows = (int64_t)nplanes * d.pz;
+  const int64_t row = (int64_t)blockIdx.x * RPB + f;
+  const bool valid = row < rows;
+  const int pl = valid ? (int)(row / d.pz) : 0;
+  const int z = valid ? (int)(row - (int64_t)pl * d.pz) : 0;
+  const int64_t fstride = (int64_t)d.pz * d.mt;  // one field of one plane
+  cd* base = inter + (int64_t)pl * 9 * fstride + (int64_t)z * d.mt;
+  const int mt = d.mt;
+  const double ir = rc[(int64_t)(plane0 + pl) * RC_N + RC_IR];
+  const double kr = d.kt * ir;  // d_theta / r multiplies mode n by i n k_theta / r
+
+  // +- pair (fields fa, fb): spectrum of v_r + i v_theta at signed index nn
+  auto pm = [&](int fa, int fb, int nn) -> cd {
+    const cd* A = base + (int64_t)fa * fstride;
+    const cd* B = base + (int64_t)fb * fstride;
+    if (nn > 0 && nn < mt) return A[nn];
+    if (nn < 0 && -nn < mt) return cconj(B[-nn]);
+    if (nn == 0) {
+      const cd p0 = A[0], m0 = B[0];
+      return cd{0.5 * (p0.x + m0.x), 0.5 * (p0.y - m0.y)};
+    }
+    return cd{0.0, 0.0};
+  };
+  // two real fields packed as x + i y: x from field fa (times i n k_theta / r
+  // when dth), y from field fb
+  auto rr = [&](int fa, bool dth, int fb, int nn) -> cd {
+    const cd* A = base + (int64_t)fa * fstride;
+    const cd* B = base + (int64_t)fb * fstride;
+    const int an = nn < 0 ? -nn : nn;
+    if (an >= mt) return cd{0.0, 0.0};
+    cd x = A[an], y = B[an];
+    if (dth) x = cd{-an * kr * x.y, an * kr * x.x};
+    if (nn == 0) return cd{x.x, y.x};
+    if (nn < 0) {
+      x = cconj(x);
+      y = cconj(y);
+    }
+    return cd{x.x - y.y, x.y + y.x};
+  };
+  // which: 0 h_u, 1 h_r, 2 h_t, 3 h_z, 4 g1, 5 g2
+  auto spec = [&](int which, int e) -> cd {
+    if (!valid) return cd{0.0, 0.0};
+    const int nn = (e <= L / 2) ? e : e - L;
+    switch (which) {
+      case 0: return pm(0, 1, nn);
+      case 1: return pm(3, 4, nn);
+      case 2: {
+        const cd v = pm(0, 1, nn);
+        const double w = nn * kr;
+        return cd{-w * v.y, w * v.x};
+      }
+      case 3: return pm(6, 7, nn);
+      case 4: return rr(2, false, 5, nn);
+      default: return rr(2, true, 8, nn);
+    }
+  };
+  typename FI::In v0;
+  auto inverse = [&](int which, typename FI::Out& out) {
+#pragma unroll
+    for (int k = 0; k < FI::PER0; ++k)
+#pragma unroll
+      for (int q = 0; q < FI::R0; ++q)
+        v0[k][q] = FI::in_valid(t, k) ? spec(which, FI::in_index(t, k, q)) : cd{0.0, 0.0};
+    FI::template run<RPB>(v0, out, bufa, bufb, W, t, f);
+  };
+  typename FI::Out hu, tmp;
+  typename FF::In hn, nz;
+  T uz[FI::PERN][FI::RN];
+  inverse(0, hu);
+  inverse(4, tmp);  // u_z + i d_r u_z
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      uz[k][q] = tmp[k][q].x;
+      nz[k][q] = {hu[k][q].x * tmp[k][q].y, 0.0};
+    }
+  inverse(1, tmp);  // d_r
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) hn[k][q] = {hu[k][q].x * tmp[k][q].x, hu[k][q].x * tmp[k][q].y};
+  inverse(2, tmp);  // d_theta / r
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T ut = hu[k][q].y;
+      hn[k][q] = {fma(ut, tmp[k][q].x, hn[k][q].x), fma(ut, tmp[k][q].y, hn[k][q].y)};
+    }
+  inverse(3, tmp);  // d_z
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T w = uz[k][q];
+      hn[k][q] = {fma(w, tmp[k][q].x, hn[k][q].x), fma(w, tmp[k][q].y, hn[k][q].y)};
+    }
+  inverse(5, tmp);  // d_theta u_z / r + i d_z u_z
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T ur = hu[k][q].x, ut = hu[k][q].y;
+      nz[k][q].x = fma(ut, tmp[k][q].x, fma(uz[k][q], tmp[k][q].y, nz[k][q].x));
+      // curvature: i (u_theta / r) h_u
+      const T c = ut * ir;
+      hn[k][q] = {fma(-c, ut, hn[k][q].x), fma(c, ur, hn[k][q].y)};
+    }
+  typename FF::Out o;
+  FF::template run<RPB>(hn, o, bufa, bufb, W, t, f);
+  if (valid) {
+    cd* Bp = base;
+    cd* Bm = base + fstride;
+#pragma unroll
+    for (int k = 0; k < FF::PERN; ++k)
+      if (FF::out_valid(t, k))
+#pragma unroll
+        for (int s2 = 0; s2 < FF::RN; ++s2) {
+          const int e = FF::out_index(t, k, s2);
+          if (e < mt) Bp[e] = o[k][s2];
+          if (e == 0) Bm[0] = cconj(o[k][s2]);
+          else if (L - e < mt) Bm[L - e] = cconj(o[k][s2]);
+        }
+  }
+  FF::template run<RPB>(nz, o, bufa, bufb, W, t, f);
+  if (valid) {
+    cd* Bz = base + 2 * fstride;
 #pragma unroll
     for (int k = 0; k < FF::PERN; ++k)
       if (FF::out_valid(t, k))
@@ -699,7 +898,12 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
 }
 
 // ------------------------------------------------------------------ dispatch
-#define TC_FFT_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+// Supported transform lengths: 2^k, 3 2^k, 9 2^k, 5 2^k and 15 2^k from 16 to
+// 2048 (radices 8, 4, 2, 3, 5), among them the paper's 320, 384, 640 and the
+// dealiased 480, 960 of its 320- and 640-point axial grids.
+#define TC_FFT_LENGTHS(X)                                                                                        \
+  X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(120) X(128) X(144) X(160) X(192) X(240) X(256) X(288) X(320) \
+  X(384) X(480) X(512) X(576) X(640) X(768) X(960) X(1024) X(1152) X(1280) X(1536) X(1920) X(2048)
 
 bool fft_length_supported(int L) {
 #define TC_CASE(LL) if (L == LL) return true;
@@ -708,9 +912,11 @@ bool fft_length_supported(int L) {
   return false;
 }
 
+int inter_fields(const tc_ctx* c) { return c->d.form == TC_CONVECTIVE ? 9 : 6; }
+
 size_t inter_bytes_per_plane(const tc_ctx* c) {
   const size_t el = (c->g.precision == TC_FP32_BULK) ? sizeof(cf) : sizeof(cd);
-  return (size_t)6 * c->d.pz * c->d.mt * el;
+  return (size_t)inter_fields(c) * c->d.pz * c->d.mt * el;
 }
 
 // Workgroups of a z kernel: with prefetching a few per CU (256 CUs), each
@@ -836,11 +1042,52 @@ hipError_t launch_theta_adj(tc_ctx* c, int np, void* inter) {
   return hipErrorInvalidValue;
 }
 
+template <int L>
+static hipError_t run_theta_conv(tc_ctx* c, int plane0, int np) {
+  using TS = TShape<double, L>;
+  const size_t lds = TS::LDS;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_theta_conv<L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  const int64_t rows = (int64_t)np * c->d.pz;
+  const unsigned blocks = (unsigned)((rows + TS::RPB - 1) / TS::RPB);
+  hipLaunchKernelGGL((k_theta_conv<L>), dim3(blocks), dim3(TS::TPF * TS::RPB), lds, c->stream, c->d, plane0, np,
+                     reinterpret_cast<cd*>(c->inter), c->tw_t, c->rc_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_conv(tc_ctx* c, int plane0, int np) {
+#define TC_CASE(LL) \
+  if (c->d.pt == LL) return run_theta_conv<LL>(c, plane0, np);
+  TC_FFT_LENGTHS(TC_CASE)
+#undef TC_CASE
+  return hipErrorInvalidValue;
+}
+
+// Convective form: u+-, u_z, their radial derivatives and (multiplied by
+// i b in the load) their axial derivatives, 9 fields per plane.
+hipError_t launch_zinv_conv(tc_ctx* c, int plane0, int np, const cd* u, const cd* du) {
+  ZIo io{};
+  for (int k = 0; k < 3; ++k) {
+    io.src[k] = u + k * c->d.F;
+    io.src[3 + k] = du + k * c->d.F;
+    io.src[6 + k] = u + k * c->d.F;
+    io.mulb[6 + k] = 1;
+  }
+  for (int k = 0; k < 9; ++k) io.zmax_slot[k] = -1;
+  io.nfields = 9;
+  io.nf_plane = 9;
+  return launch_zinv_io(c, plane0, np, io, c->inter, false);
+}
+
 hipError_t launch_zfwd(tc_ctx* c, int plane0, int np, cd* N) {
   ZIo io{};
   for (int k = 0; k < 3; ++k) io.dst[k] = N + k * c->d.F;
   io.nfields = 3;
-  io.nf_plane = 6;
+  io.nf_plane = inter_fields(c);
   io.scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
   io.weights = 0;
   return launch_zfwd_io(c, plane0, np, io, c->inter, c->g.precision == TC_FP32_BULK);

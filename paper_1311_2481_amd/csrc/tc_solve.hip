@@ -130,6 +130,84 @@ hipError_t launch_factor(tc_ctx* c, int* bad_dev) {
   return hipGetLastError();
 }
 
+// Check of the unpivoted factors (the paper's DGBTRF pivots): for every
+// operator and distinct mode, solve A x = A x0 with x0_j = 1 + sin(0.7 j)/2
+// by the stored factors and take the componentwise backward error
+// max_j |A x - b|_j / (|A| |x| + |b|)_j (Oettli-Prager).  A backward-stable
+// elimination gives a few units of rounding; element growth without
+// pivoting would show here.  tmp: n_r doubles per (op, mode) lane; worst:
+// the largest error over all lanes, as the bits of a non-negative double.
+__global__ void k_factor_check(const double* __restrict__ rc, const double* __restrict__ fac, Dims d,
+                               double* __restrict__ tmp, unsigned long long* worst) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = NOPS * d.ndm;
+  if (gid >= total) return;
+  const int op = gid / d.ndm, dm = gid - op * d.ndm;
+  const int labs = dm / d.mt, n = dm - labs * d.mt;
+  const double a = n * d.kt, b = labs * d.kz;
+  const bool rev = (op != OP_P);
+  const int M = d.n_r - 1;
+  auto x0 = [](int j) { return 1.0 + 0.5 * sin(0.7 * j); };
+  auto T = [&](int ip) -> double& { return tmp[(int64_t)ip * total + gid]; };
+  // b = A x0 and the forward sweep, in the factor's row order
+  double w[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ip = 0; ip <= M; ++ip) {
+    const int j = rev ? M - ip : ip;
+    double row[NB9];
+    operator_row(rc, d, op, j, a, b, row);
+    double bj = 0.0;
+    for (int k = 0; k < NB9; ++k) {
+      const int node = j + k - HW;
+      if (node >= 0 && node <= M) bj = fma(row[k], x0(node), bj);
+    }
+    const double* F = facp(fac, d, op, j) + dm;
+    double y = bj;
+    for (int q = 0; q < 4; ++q) y -= F[(int64_t)q * d.ndm] * w[q];
+    for (int q = 3; q >= 1; --q) w[q] = w[q - 1];
+    w[0] = y;
+    T(ip) = y;
+  }
+  // back-substitution
+  for (int q = 0; q < 4; ++q) w[q] = 0.0;
+  for (int ip = M; ip >= 0; --ip) {
+    const int j = rev ? M - ip : ip;
+    const double* F = facp(fac, d, op, j) + dm;
+    double y = T(ip);
+    for (int c = 1; c <= 4; ++c) y -= F[(int64_t)(4 + c) * d.ndm] * w[c - 1];
+    y *= F[(int64_t)4 * d.ndm];
+    for (int q = 3; q >= 1; --q) w[q] = w[q - 1];
+    w[0] = y;
+    T(ip) = y;
+  }
+  // residual, row by row in natural order (x_j is T(ip(j)))
+  double err = 0.0;
+  for (int j = 0; j <= M; ++j) {
+    double row[NB9];
+    operator_row(rc, d, op, j, a, b, row);
+    double r = 0.0, den = 0.0, bj = 0.0;
+    for (int k = 0; k < NB9; ++k) {
+      const int node = j + k - HW;
+      if (node < 0 || node > M) continue;
+      const double xk = T(rev ? M - node : node);
+      r = fma(row[k], xk, r);
+      den = fma(fabs(row[k]), fabs(xk), den);
+      bj = fma(row[k], x0(node), bj);
+    }
+    r -= bj;
+    den += fabs(bj);
+    if (den > 0.0) err = fmax(err, fabs(r) / den);
+  }
+  if (!(err <= 1.0)) err = 1.0;  // a non-finite residual counts as the worst
+  atomicMax(worst, (unsigned long long)__double_as_longlong(err));
+}
+
+hipError_t launch_factor_check(tc_ctx* c, double* tmp, unsigned long long* worst_dev) {
+  const int total = NOPS * c->d.ndm;
+  hipLaunchKernelGGL(k_factor_check, dim3((total + 63) / 64), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, tmp,
+                     worst_dev);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ standalone solve
 // One operator, every mode.  The first sweep writes its intermediate into x,
 // the second sweep overwrites it with the solution (x may alias rhs).
@@ -193,6 +271,8 @@ hipError_t launch_solve(tc_ctx* c, int op, int transposed, const cd* rhs, cd* x)
 //                first (descending) sweep of H+, H-, H_z                 -> z     (in u_next), p* (in p)
 //  3 ascending : u* by the second sweep; RHS of phi; forward sweep of P  -> u* (in u_next), y_phi (in N_prev[0])
 //  4 descending: phi by back-substitution; correction and pressure update -> u^{i+1} (in u_next), p
+//                (mode (0,0): the correction removes u*_r entirely, the exact
+//                solution of eq. correction for that mode)
 // Stencil terms lag the sweep by 4 rows (the D1 stencil spans +-4 rows);
 // in the ascending sweeps D1 is applied in scatter form (each new row adds
 // its contribution to the 9 rows it touches), so no input window is kept.
@@ -706,8 +786,13 @@ __global__ __launch_bounds__(64) void k_pc4(TC_PC_ARGS) {
     for (int k = 0; k < NB9; ++k) d1 = cfma(d1, R[RC_W1 + k], fw[k]);
     const cd ph = fw[HW];
     const int64_t o = i * S + L.o;
-    const cd v[3] = {csub(us[0], cnfma(d1, a * ir, ph)), csub(us[1], cfma(d1, a * ir, ph)),
-                     csub(us[2], cimul(ph, L.b))};
+    cd v[3] = {csub(us[0], cnfma(d1, a * ir, ph)), csub(us[1], cfma(d1, a * ir, ph)), csub(us[2], cimul(ph, L.b))};
+    if (L.zero_mode) {
+      // mode (0,0): d_r phi = u*_r solves eq. correction exactly for this
+      // mode, so the radial velocity is removed and u_theta, u_z are kept
+      v[0] = cmuls(csub(us[0], us[1]), 0.5);
+      v[1] = cd{-v[0].x, -v[0].y};
+    }
     un[o] = v[0];
     un[F + o] = v[1];
     un[2 * F + o] = v[2];
@@ -901,7 +986,8 @@ hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
 // saturates HBM on large grids) down.
 static bool pc_chunked(const tc_ctx* c) { return (c->d.ndm + 31) / 32 < 2 * 4 * 256; }
 
-bool pc_fuses_curl(const tc_ctx* c) { return TC_FUSE_CURL && !pc_chunked(c); }
+// (only the rotational form transforms the curl)
+bool pc_fuses_curl(const tc_ctx* c) { return TC_FUSE_CURL && !pc_chunked(c) && c->d.form == TC_ROTATIONAL; }
 
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
                      int want_p, cd* omega_out) {

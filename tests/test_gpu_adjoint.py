@@ -11,7 +11,7 @@ import oracle
 import tc_inputs
 from oracle import adjoint as adj
 from oracle import diagnostics as dg
-from gpu_common import make_pair, rel_l2, to_dev, to_host
+from gpu_common import floor_tol, make_pair, rel_l2, to_dev, to_host, twin_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -26,8 +26,11 @@ def test_adjoint_step_matches_oracle(name, hermitian):
     out = to_host(S.step_adjoint(to_dev(np.concatenate([u, u])), to_dev(np.concatenate([a, b, c]))))
     ref = adj.step_adjoint(P, u, a, b, c)
     errs = [rel_l2(out[3 * k:3 * k + 3], ref[k]) for k in range(3)]
-    print(f"{name} adjoint step (hermitian={hermitian}): rel_l2 u {errs[0]:.2e}, u_prev {errs[1]:.2e}, N_prev {errs[2]:.2e}")
-    assert max(errs) < (1e-12 if name == "small" else 1e-9)
+    floors = [twin_floor(P, lambda Q: adj.step_adjoint(Q, u, a, b, c)[k], ref[k]) for k in range(3)]
+    print(f"{name} adjoint step (hermitian={hermitian}): rel_l2 u {errs[0]:.2e}, u_prev {errs[1]:.2e}, "
+          f"N_prev {errs[2]:.2e}; floors {floors[0]:.2e} {floors[1]:.2e} {floors[2]:.2e}")
+    for e, f in zip(errs, floors):
+        assert e <= floor_tol(f)
     S.close()
 
 
@@ -70,18 +73,25 @@ def test_differentiation_workload_gradient_vs_finite_differences():
         S.step(T)
         return S.diag()["perturbation_energy"]
 
+    # Central differences with steps eps |pert|: truncation error ~ eps^2
+    # (relative, the map being smooth on the scale |pert|), rounding error
+    # ~ 1e-16 J / (eps |<g, v>|) ~ 1e-16 / eps here (J ~ |<g, v>|, both
+    # quadratic in the perturbation), so eps = 1e-4 and 1e-5 both sit near
+    # the 1e-8..1e-11 optimum.  The adjoint must agree with the differences
+    # at BOTH steps.
     worst = 0.0
     for seed in range(1000, 1008):
         v = tc_inputs.random_direction(r, cfg, seed)
         v *= np.linalg.norm(pert) / np.linalg.norm(v)
         ad = adj.inner(g, v)
-        best = np.inf
-        for eps in (1e-3, 1e-4, 1e-5):
+        mism = []
+        for eps in (1e-4, 1e-5):
             fd = (J_of(u0 + eps * v) - J_of(u0 - eps * v)) / (2 * eps)
-            best = min(best, abs(fd - ad) / abs(ad))
-        worst = max(worst, best)
-        print(f"direction {seed}: adjoint {ad:.10e}, best relative FD mismatch {best:.2e}")
-    print(f"J = {J:.10e}; worst over 8 directions: {worst:.2e}")
+            mism.append(abs(fd - ad) / abs(ad))
+        worst = max(worst, max(mism))
+        print(f"direction {seed}: adjoint {ad:.10e}, relative FD mismatch {mism[0]:.2e} (eps 1e-4), "
+              f"{mism[1]:.2e} (eps 1e-5)")
+    print(f"J = {J:.10e}; worst over 8 directions and both steps: {worst:.2e}")
     assert worst < 1e-6
     S.close()
 

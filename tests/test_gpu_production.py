@@ -14,6 +14,7 @@ import oracle
 import tc_inputs
 from oracle import nonlinear as nl
 from oracle import scheme
+from gpu_common import floor_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -62,13 +63,20 @@ def test_production_nonlinear_sampled_planes():
         num += np.sum(np.abs(got - ref) ** 2)
         den += np.sum(np.abs(ref) ** 2)
         print(f"production nonlinear plane {j}: rel_l2={err:.2e} (one-ulp D1 floor {floor:.2e})")
-        assert err <= max(20.0 * floor, 1e-12)
+        assert err <= floor_tol(floor, minimum=1e-13)
         assert np.all(got[:, cfg.m_z // 2] == 0)
     total = np.sqrt(num / den)
     print(f"production nonlinear, 8 sampled planes together: rel_l2={total:.2e}")
     assert total < 1e-11
     del u, N
     torch.cuda.empty_cache()
+
+
+def test_production_factor_backward_error():
+    S, P, cfg = solver()
+    err = S.factor_backward_error()
+    print(f"production: largest componentwise backward error of the factors {err:.2e}")
+    assert 0.0 < err < 1e-14
 
 
 @pytest.mark.parametrize("kind", ["P", "Up", "Um", "Uz"])
@@ -81,22 +89,25 @@ def test_production_solve_sampled_modes(kind):
     rng = np.random.Generator(np.random.PCG64(8))
     picks = [(0, 0), (0, 1), (1, 0), (cfg.m_z // 2 - 1, cfg.m_theta - 1)]
     picks += [(int(rng.integers(cfg.m_z // 2)), int(rng.integers(cfg.m_theta))) for _ in range(252)]
-    num = den = 0.0
+    num = den = fl = 0.0
     for labs, n in picks:
         slots = [labs] if labs == 0 else [labs, cfg.m_z - labs]
         b = rhs[:, slots, n].cpu().numpy()
         cols = np.concatenate([np.stack([b[:, k].real, b[:, k].imag], 1) for k in range(len(slots))], 1)
         ref = P.solve_mode(kind, n, labs, np.ascontiguousarray(cols))
+        dense = np.linalg.solve(P.operator(kind, n, labs), cols)
         got = x[:, slots, n].cpu().numpy()
         for k in range(len(slots)):
             r = ref[:, 2 * k] + 1j * ref[:, 2 * k + 1]
             num += np.sum(np.abs(got[:, k] - r) ** 2)
+            fl += np.sum(np.abs(dense[:, 2 * k] + 1j * dense[:, 2 * k + 1] - r) ** 2)
             den += np.sum(np.abs(r) ** 2)
-    err = np.sqrt(num / den)
-    print(f"production solve {kind}, 256 sampled modes rel_l2={err:.3e}")
+    err, floor = np.sqrt(num / den), np.sqrt(fl / den)
+    print(f"production solve {kind}, 256 sampled modes rel_l2={err:.3e} (dense-vs-banded floor {floor:.2e})")
     # the Neumann Poisson operator is ill conditioned at n_r = 512 (smallest
-    # near-wall spacing ~1e-5): two LU solvers differ at ~1e-10 there
-    assert err < (1e-8 if kind == "P" else 1e-12)
+    # near-wall spacing ~1e-5): any two backward-stable solvers differ at
+    # its conditioning level, the floor measured here
+    assert err < floor_tol(floor)
     del rhs, x
     torch.cuda.empty_cache()
 
@@ -185,7 +196,7 @@ def test_production_two_steps_sampled():
     eu, fu, ep, fp = (np.sqrt(v / len(picks)) for v in (eu, fu, ep, fp))
     print(f"production step, {len(picks)} sampled modes: u rel_l2 {eu:.2e} (one-ulp node floor {fu:.1e}), "
           f"p rel_l2 {ep:.2e} (floor {fp:.1e})")
-    assert eu <= max(20 * fu, 1e-12) and ep <= max(20 * fp, 1e-10)
+    assert eu <= floor_tol(fu) and ep <= floor_tol(fp)
 
     # 2. a second step: its nonlinear term uses the curl of u^{i+1} formed by
     #    the first step's last sweep; it must equal the standalone nonlinear
@@ -212,10 +223,114 @@ def test_production_two_steps_sampled():
         got = N1[:, j].cpu().numpy()
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"production second-step nonlinear plane {j}: rel_l2={err:.2e} (one-ulp D1 floor {floor:.2e})")
-        assert err <= max(20.0 * floor, 1e-12)
+        assert err <= floor_tol(floor, minimum=1e-13)
         num += np.sum(np.abs(got - ref) ** 2)
         den += np.sum(np.abs(ref) ** 2)
     assert np.sqrt(num / den) < 1e-11
     assert S.check_finite()
     del u1, N1
     torch.cuda.empty_cache()
+
+
+def _nonlinear_float32_at(P, window, j):
+    """Yardstick of the FP32-bulk form on plane j: the oracle's curl in
+    double, then the transforms and products in single precision (scipy.fft
+    keeps float32), i.e. the rounding any float32 evaluation incurs."""
+    import scipy.fft as sfft
+    lo = max(0, j - 4)
+    ur, ut, uz = nl.cylindrical(window)
+    w = P.D1[j, lo:lo + window.shape[1]]
+    d_ut = np.tensordot(w, ut, axes=(0, 0))
+    d_uz = np.tensordot(w, uz, axes=(0, 0))
+    k = j - lo
+    wr, wt, wz = nl._curl(P, P.r[j], ur[k], ut[k], uz[k], d_ut, d_uz)
+
+    def phys(f):
+        return sfft.irfft2(nl._pad(P, f).astype(np.complex64), s=(P.p_z, P.p_theta), axes=(-2, -1),
+                           norm="forward")
+    U, W = phys(np.stack([ur[k], ut[k], uz[k]])), phys(np.stack([wr, wt, wz]))
+    prod = np.stack([W[1] * U[2] - W[2] * U[1], W[2] * U[0] - W[0] * U[2], W[0] * U[1] - W[1] * U[0]])
+    return nl.plus_minus(*nl._truncate(P, sfft.rfft2(prod, axes=(-2, -1), norm="forward")))
+
+
+def test_production_fp32_bulk():
+    """The FP32-bulk form at the size whose throughput the benchmark
+    reports: its nonlinear term on the sampled planes within a small factor
+    of what float32 transforms of the same spectra give, and a whole step on
+    sampled modes (the predictor-corrector stays FP64) against the oracle
+    fed with the library's N^i, within 10x the one-ulp node floor."""
+    import torch
+    from paper_1311_2481_amd import Solver
+    # the FP64 context goes first: both together would hold ~250 GB
+    if "S" in _state:
+        _state.pop("S").close()
+        torch.cuda.empty_cache()
+    cfg = tc_inputs.Config(tc_inputs.CONFIGS["production"])
+    P = oracle.Problem(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+    S = Solver(cfg.n_r, cfg.m_theta, cfg.m_z, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt, precision="fp32_bulk")
+    try:
+        u = tc_inputs.initial_state(P.r, cfg, device="cuda")
+        N = S.nonlinear(u)
+        torch.cuda.synchronize()
+        for j in PLANES:
+            lo, hi = max(0, j - 4), min(cfg.n_r - 1, j + 4)
+            window = u[:, lo:hi + 1].cpu().numpy()
+            ref = nl.nonlinear_rot_at(P, window, j)
+            yard = np.linalg.norm(_nonlinear_float32_at(P, window, j) - ref) / np.linalg.norm(ref)
+            err = np.linalg.norm(N[:, j].cpu().numpy() - ref) / np.linalg.norm(ref)
+            print(f"production FP32-bulk nonlinear plane {j}: rel_l2={err:.2e} (float32 yardstick {yard:.2e})")
+            assert err < 8.0 * yard
+        del N
+        # one step on sampled modes
+        mz, mt = cfg.m_z, cfg.m_theta
+        rng = np.random.Generator(np.random.PCG64(22))
+        picks = [(0, 0), (0, 1), (1, 0), (mz // 2 - 1, mt - 1)]
+        picks += [(int(rng.integers(mz // 2)), int(rng.integers(mt))) for _ in range(28)]
+        cols = [(s, n) for labs, n in picks for s in ([labs] if labs == 0 else [labs, mz - labs])]
+        si = torch.tensor([c[0] for c in cols], device="cuda")
+        ni = torch.tensor([c[1] for c in cols], device="cuda")
+
+        def at(t):
+            return t[:, :, si, ni].cpu().numpy()
+
+        up = tc_inputs.initial_state(P.r, tc_inputs.Config(cfg, seed=4), device="cuda")
+        Np = S.nonlinear(up)
+        U, UP, NP = at(u), at(up), at(Np)
+        S.set_state(u, up, Np)
+        del up, Np
+        S.step(1)
+        u1, p1 = S.get_state()
+        _, NI_t = S.get_history()
+        U1, P1, NI = at(u1), p1[:, si, ni].cpu().numpy(), at(NI_t)
+        del u1, p1, NI_t, u
+        torch.cuda.empty_cache()
+        T = oracle.Problem(cfg.n_r, 2, 4, cfg.eta, cfg.Re_i, cfg.Re_o, cfg.dt)
+        TJ = _node_jittered(T, 6)
+        eu = ep = fu = fp = 0.0
+        k = 0
+        for labs, n in picks:
+            ns = 1 if labs == 0 else 2
+            refs = []
+            for base in (T, TJ):
+                Q, nq, sq = _mode_problem(base, labs, n, cfg.k_theta, cfg.k_z)
+                ins = [Q.zeros(3) for _ in range(4)]
+                for src, dst in zip((U, UP, NI, NP), ins):
+                    for m in range(ns):
+                        dst[:, :, sq[m], nq] = src[:, :, k + m]
+                un, pn = scheme.predictor_corrector(Q, ins[2], ins[3], ins[0], ins[1])
+                refs.append((un[:, :, sq, nq], pn[:, sq, nq]))
+            (ru, rp), (ju, jp) = refs
+            gu, gp = U1[:, :, k:k + ns], P1[:, k:k + ns]
+            nu_, np_ = np.sum(np.abs(ru) ** 2), np.sum(np.abs(rp) ** 2)
+            eu += np.sum(np.abs(gu - ru) ** 2) / nu_
+            fu += np.sum(np.abs(ju - ru) ** 2) / nu_
+            ep += np.sum(np.abs(gp - rp) ** 2) / np_
+            fp += np.sum(np.abs(jp - rp) ** 2) / np_
+            k += ns
+        eu, fu, ep, fp = (np.sqrt(v / len(picks)) for v in (eu, fu, ep, fp))
+        print(f"production FP32-bulk step, {len(picks)} sampled modes: u rel_l2 {eu:.2e} (floor {fu:.1e}), "
+              f"p rel_l2 {ep:.2e} (floor {fp:.1e})")
+        assert eu <= floor_tol(fu) and ep <= floor_tol(fp)
+    finally:
+        S.close()
+        torch.cuda.empty_cache()

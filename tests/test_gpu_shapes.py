@@ -21,7 +21,8 @@ from gpu_common import rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-LENGTHS = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+LENGTHS = [16, 24, 32, 40, 48, 64, 80, 96, 120, 128, 144, 160, 192, 240, 256, 288, 320, 384, 480, 512, 576,
+           640, 768, 960, 1024, 1152, 1280, 1536, 1920, 2048]
 # theta length i is paired with z length i + 5 (cyclically): every length is
 # used once along theta and once along z
 CASES = [(LENGTHS[i], LENGTHS[(i + 5) % len(LENGTHS)]) for i in range(len(LENGTHS))]
