@@ -318,6 +318,7 @@ hipError_t adjoint_nonlinear(tc_ctx* c, const cd* u, const cd* nbar, const cd* k
   // the transpose of the forward transform carries its 1/(P_theta P_z)
   zo.scale = 1.0 / ((double)d.pt * (double)d.pz);
   zo.weights = 1;
+  adjoint_field_map(zo);
   e = launch_zinv_io(c, 0, d.n_r, zi, inter, false);
   if (e == hipSuccess) e = launch_theta_adj(c, d.n_r, inter);
   if (e == hipSuccess) e = launch_zfwd_io(c, 0, d.n_r, zo, inter, false);

@@ -65,6 +65,10 @@ struct ZIo {
   unsigned int* zmax;
   int zmax_slot[9];
   int mulb[9];  // inverse kernel: input field k is multiplied by i l k_z (its z derivative) when set
+  // forward kernel: when use_map is set, output k is transformed from the
+  // intermediate's field src_field[k] (else from field k)
+  int use_map;
+  int src_field[9];
 };
 
 struct Dims {
@@ -146,6 +150,9 @@ hipError_t launch_zfwd(tc_ctx* c, int plane0, int nplanes, cd* N);
 hipError_t launch_zinv_io(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, bool f32);
 hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32);
 hipError_t launch_theta_adj(tc_ctx* c, int nplanes, void* inter);
+// which intermediate fields the axial forward pass of the adjoint reads
+// (where the azimuthal adjoint kernel leaves its six results)
+void adjoint_field_map(ZIo& zo);
 // convective form: radial derivatives D1 u (3 fields) and the azimuthal
 // pass over the 9-field intermediate of planes plane0 ..
 hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du);

@@ -183,9 +183,8 @@ hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du) { return run_curl<1>(c, u, 
 // ------------------------------------------------------------------ launch shapes
 // z kernels: NF columns per workgroup, TPF threads per column; in-place LDS.
 // Swizzled (unpadded) LDS layout in the z kernels (1: FP64 only, 2: both
-// precisions): it removes their bank conflicts.  Persistent prefetching z
-// workgroups (TC_Z_PREFETCH) are kept as an option for float data; one tile
-// per workgroup measured as fast and uses far fewer VGPRs.
+// precisions): it removes their bank conflicts.  One column tile per
+// workgroup.
 // Tile width: up to TC_Z_WG threads (twice that for the wide shape below) and TC_Z_LDS_CAP bytes of LDS per workgroup, which at 1536 points
 // gives 4 FP64 (8 float) columns, 64 bytes of every row.  Narrower tiles (2 FP64 columns, 32 bytes per row, three
 // workgroups per CU) wrote about 1.4x their bytes to HBM and ran at a speed
@@ -194,9 +193,6 @@ hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du) { return run_curl<1>(c, u, 
 // one workgroup per CU.
 #ifndef TC_Z_SWIZZLE
 #define TC_Z_SWIZZLE 2
-#endif
-#ifndef TC_Z_PREFETCH
-#define TC_Z_PREFETCH 0
 #endif
 #ifndef TC_Z_LDS_CAP
 #define TC_Z_LDS_CAP 131072
@@ -217,28 +213,14 @@ template <typename T, int L> struct ZShape {
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
   static_assert(NF >= 1, "transform too long for LDS");
   static constexpr size_t LDS = (size_t)lds_len<L, SWZ>() * NF * sizeof(C2<T>);
-  // persistent workgroups prefetching the next tile: pays off when the
-  // prefetch registers do not lower the occupancy (float data)
-  static constexpr bool PREFETCH = TC_Z_PREFETCH && sizeof(T) == 4;
 };
-// theta kernel: TPF threads per row, RPB rows per workgroup; ping-pong
-// LDS (one barrier per exchange) or in place (two barriers, half the LDS).
-// TC_THETA_TPF8: L/8 threads per row with the inverse transform's radices
-// in reversed order, so that its last pass (and the forward transform's
-// first) is radix 8 with every thread busy.
-#ifndef TC_THETA_PINGPONG
-#define TC_THETA_PINGPONG 0
-#endif
-#ifndef TC_THETA_TPF8
-#define TC_THETA_TPF8 0
-#endif
+// theta kernel: TPF threads per row, RPB rows per workgroup, the LDS
+// exchanges in place (two barriers each).
 template <typename T, int L> struct TShape {
-  static constexpr bool TPF8 = TC_THETA_TPF8 && L % 8 == 0 && L >= 512;
-  static constexpr int TPF = TPF8 ? L / 8 : ((L % 6 == 0) ? L / 6 : L / 8);
-  static constexpr bool FIREV = TPF8;  // radix order of the inverse transform
+  static constexpr int TPF = (L % 6 == 0) ? L / 6 : L / 8;
+  static constexpr bool FIREV = false;  // radix order of the inverse transform
   static constexpr int RPB = TPF >= 256 ? 1 : 256 / TPF;
-  static constexpr int NBUF = TC_THETA_PINGPONG ? 2 : 1;
-  static constexpr size_t LDS = NBUF * (size_t)lds_len<L, false>() * RPB * sizeof(C2<T>);
+  static constexpr size_t LDS = (size_t)lds_len<L, false>() * RPB * sizeof(C2<T>);
 };
 
 // Output weight of the forward z kernel for field fld at azimuthal index n:
@@ -251,37 +233,17 @@ __device__ __forceinline__ double z_out_weight(int weights, int fld, int n) {
   return n == 0 ? 1.0 : 2.0;
 }
 
-// Tile walk of the persistent z kernels: workgroup b belongs to XCD group b % G; the
-// groups own contiguous, disjoint tile ranges that together cover every
-// tile, and the workgroups of a group stride through its range starting at
-// their slot b / G.  G = 8 (workgroups are dispatched round
-// robin over the 8 XCDs, so neighbouring column tiles, which share cache
-// lines, go through the same L2), or the number of workgroups if that is
-// smaller, so that every group has at least one workgroup: every tile is
-// then transformed exactly once for any grid size.
-// With TC_Z_PREFETCH the next tile is loaded into registers while the
-// current one is transformed (persistent grids).
-// One tile per workgroup (the default): the grid is 8 ceil(ntiles / 8)
-// workgroups and workgroup b takes tile (b % 8) ceil(ntiles / 8) + b / 8, a
-// bijection that gives each XCD a contiguous range; tiles past the end
-// belong to padding workgroups, which return -1.
+// Tile walk of the z kernels: the grid is 8 ceil(ntiles / 8) workgroups
+// and workgroup b takes tile (b % 8) ceil(ntiles / 8) + b / 8, a bijection
+// that gives each XCD (workgroups are dispatched round robin over the 8
+// XCDs) a contiguous range, so neighbouring column tiles, which share cache
+// lines, go through the same L2; tiles past the end belong to padding
+// workgroups, which return -1.
 __device__ __forceinline__ int single_tile(int ntiles) {
   const int per = (ntiles + 7) / 8;
   const int id = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   return id < ntiles ? id : -1;
 }
-
-struct TileWalk {
-  int per_group, first, last;
-  __device__ TileWalk(int ntiles) {
-    const int g = gridDim.x;
-    const int G = g < 8 ? g : 8;
-    const int grp = blockIdx.x % G;
-    per_group = (g - grp + G - 1) / G;  // workgroups in this group
-    first = (int)((int64_t)ntiles * grp / G) + (int)(blockIdx.x / G);
-    last = (int)((int64_t)ntiles * (grp + 1) / G);
-  }
-};
 
 // ------------------------------------------------------------------ z inverse
 template <typename T, int L>
@@ -354,28 +316,12 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
     // non-negative floats order as their bit patterns
     if ((threadIdx.x & 63) == 0) atomicMax(io.zmax + ZMAX_WORDS * pl + which, __float_as_uint(m));
   };
-  if constexpr (Z::PREFETCH) {
-    cd cur[FI::PER0][FI::R0], nxt[FI::PER0][FI::R0];
-    TileWalk tw(ntiles);
-    if (tw.first < tw.last) load(tw.first, cur);
-    for (int id = tw.first; id < tw.last; id += tw.per_group) {
-      const int idn = id + tw.per_group;
-      if (idn < tw.last) load(idn, nxt);
-      record(id, cur);
-      transform_store(id, cur);
-#pragma unroll
-      for (int k = 0; k < FI::PER0; ++k)
-#pragma unroll
-        for (int q = 0; q < FI::R0; ++q) cur[k][q] = nxt[k][q];
-    }
-  } else {
-    const int id = single_tile(ntiles);
-    if (id < 0) return;  // padding workgroup (uniform over the workgroup)
-    cd cur[FI::PER0][FI::R0];
-    load(id, cur);
-    record(id, cur);
-    transform_store(id, cur);
-  }
+  const int id = single_tile(ntiles);
+  if (id < 0) return;  // padding workgroup (uniform over the workgroup)
+  cd cur[FI::PER0][FI::R0];
+  load(id, cur);
+  record(id, cur);
+  transform_store(id, cur);
 }
 
 // ------------------------------------------------------------------ theta pass
@@ -400,7 +346,7 @@ void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter, const C2<T>* __rest
   static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
   extern __shared__ unsigned char lds_raw[];
   C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
-  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
+  C2<T>* bufb = bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -536,10 +482,15 @@ void k_theta(Dims d, int nplanes, C2<T>* __restrict__ inter, const C2<T>* __rest
 // The products are accumulated as each inverse transform completes, so at
 // most h_u, u_z and the two accumulators are held.  Outputs overwrite
 // fields 0-2 of the row, as in the rotational kernel.
+// (2 waves per SIMD at lengths >= 1024: the six inverse transforms' held
+// fields and accumulators do not fit 3 or 4 waves' budgets without spilling)
+#ifndef TC_THETA_CONV_WAVES
+#define TC_THETA_CONV_WAVES 2
+#endif
 template <int L>
 __global__ __launch_bounds__((TShape<double, L>::TPF * TShape<double, L>::RPB))
 #if TC_THETA_WAVES
-__attribute__((amdgpu_waves_per_eu(L >= 1024 ? TC_THETA_WAVES : 1)))
+__attribute__((amdgpu_waves_per_eu(L >= 1024 ? TC_THETA_CONV_WAVES : 1)))
 #endif
 void k_theta_conv(Dims d, int plane0, int nplanes, cd* __restrict__ inter, const cd* __restrict__ W,
                   const double* __restrict__ rc) {
@@ -551,7 +502,7 @@ void k_theta_conv(Dims d, int plane0, int nplanes, cd* __restrict__ inter, const
   static_assert(FI::RN == FF::R0 && FI::PERN == FF::PER0, "mirrored transforms must line up");
   extern __shared__ unsigned char lds_raw[];
   cd* bufa = reinterpret_cast<cd*>(lds_raw);
-  cd* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
+  cd* bufb = bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -705,9 +656,17 @@ void k_theta_conv(Dims d, int plane0, int nplanes, cd* __restrict__ inter, const
 // forward transforms of u_bar_r + i u_bar_theta, omega_bar_r + i
 // omega_bar_theta and u_bar_z + i omega_bar_z give (after the axial pass with
 // Hermitian weights) the cotangents of u+-, omega+-, u_z, omega_z.  The six
-// results overwrite fields 0-5 of the row.
+// results overwrite fields of the row that have been consumed: u_bar+- go
+// to fields 6, 7 (see adjoint_field_map), omega_bar+- to 2, 3 and u_bar_z,
+// omega_bar_z to 4, 5.  The transforms are staged so that few spectra are
+// held at once (3 waves per SIMD at the long lengths: 78.8 ms against 82.9
+// ms for the adjoint step at scale with all five inverse spectra held).
 template <typename T, int L>
-__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_theta_adj(Dims d, int nplanes,
+#ifndef TC_THETA_ADJ_WAVES
+#define TC_THETA_ADJ_WAVES 3
+#endif
+__global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB))
+__attribute__((amdgpu_waves_per_eu(L >= 1024 ? TC_THETA_ADJ_WAVES : 1))) void k_theta_adj(Dims d, int nplanes,
                                                                                      C2<T>* __restrict__ inter,
                                                                                      const C2<T>* __restrict__ W) {
   using TS = TShape<T, L>;
@@ -716,7 +675,7 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
   using FF = Fft<T, L, TPF, -1, !TS::FIREV>;
   extern __shared__ unsigned char lds_raw[];
   C2<T>* bufa = reinterpret_cast<C2<T>*>(lds_raw);
-  C2<T>* bufb = TS::NBUF == 2 ? bufa + lds_len<L, false>() * RPB : bufa;
+  C2<T>* bufb = bufa;
   const int f = threadIdx.x % RPB, t = threadIdx.x / RPB;
   const int64_t rows = (int64_t)nplanes * d.pz;
   const int64_t row = (int64_t)blockIdx.x * RPB + f;
@@ -764,24 +723,37 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
         v0[k][q] = FI::in_valid(t, k) ? spec(mode, A, B, FI::in_index(t, k, q)) : C2<T>{T(0), T(0)};
     FI::template run<RPB>(v0, out, bufa, bufb, W, t, f);
   };
-  typename FI::Out hu, hw, g, hg, gz;
-  inverse(0, fld(0), fld(1), hu);
-  inverse(0, fld(3), fld(4), hw);
-  inverse(1, fld(2), fld(5), g);
+  // The cotangent transforms first, then omega (whose products are
+  // finished and transformed at once, their outputs going to the consumed
+  // fields 6, 7), then u; at most h_g, g_z, u_z and one partial product
+  // are held between transforms.
+  typename FI::Out hg, tmp;
+  T gzr[FI::PERN][FI::RN], uzr[FI::PERN][FI::RN], wzr[FI::PERN][FI::RN], a3x[FI::PERN][FI::RN];
   inverse(2, fld(6), fld(7), hg);
-  inverse(3, fld(8), fld(8), gz);
-  typename FF::In a1, a2, a3;
+  inverse(3, fld(8), fld(8), tmp);
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) gzr[k][q] = tmp[k][q].x;
+  inverse(1, fld(2), fld(5), tmp);  // u_z + i omega_z
 #pragma unroll
   for (int k = 0; k < FI::PERN; ++k)
 #pragma unroll
     for (int q = 0; q < FI::RN; ++q) {
-      const T ur = hu[k][q].x, ut = hu[k][q].y, uz = g[k][q].x;
-      const T wr = hw[k][q].x, wt = hw[k][q].y, wz = g[k][q].y;
-      const T gr = hg[k][q].x, gt = hg[k][q].y, gzv = gz[k][q].x;
-      // u_bar = g x omega, omega_bar = u x g
-      a1[k][q] = {gt * wz - gzv * wt, gzv * wr - gr * wz};
-      a2[k][q] = {ut * gzv - uz * gt, uz * gr - ur * gzv};
-      a3[k][q] = {gr * wt - gt * wr, ur * gt - ut * gr};
+      uzr[k][q] = tmp[k][q].x;
+      wzr[k][q] = tmp[k][q].y;
+    }
+  inverse(0, fld(3), fld(4), tmp);  // omega_r + i omega_theta
+  typename FF::In a;
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T wr = tmp[k][q].x, wt = tmp[k][q].y, wz = wzr[k][q];
+      const T gr = hg[k][q].x, gt = hg[k][q].y, gzv = gzr[k][q];
+      // u_bar = g x omega; the omega part of omega_bar_z's partner below
+      a[k][q] = {gt * wz - gzv * wt, gzv * wr - gr * wz};
+      a3x[k][q] = gr * wt - gt * wr;
     }
   typename FF::Out o;
   auto store_pair = [&](int fa, int fb) {
@@ -799,9 +771,21 @@ __global__ __launch_bounds__((TShape<T, L>::TPF * TShape<T, L>::RPB)) void k_the
           else if (L - e < mt) Bm[L - e] = cconj(o[k][s2]);
         }
   };
-  FF::template run<RPB>(a1, o, bufa, bufb, W, t, f);
-  store_pair(0, 1);
-  FF::template run<RPB>(a2, o, bufa, bufb, W, t, f);
+  FF::template run<RPB>(a, o, bufa, bufb, W, t, f);
+  store_pair(6, 7);
+  inverse(0, fld(0), fld(1), tmp);  // u_r + i u_theta
+  typename FF::In a3;
+#pragma unroll
+  for (int k = 0; k < FI::PERN; ++k)
+#pragma unroll
+    for (int q = 0; q < FI::RN; ++q) {
+      const T ur = tmp[k][q].x, ut = tmp[k][q].y, uz = uzr[k][q];
+      const T gr = hg[k][q].x, gt = hg[k][q].y, gzv = gzr[k][q];
+      // omega_bar = u x g
+      a[k][q] = {ut * gzv - uz * gt, uz * gr - ur * gzv};
+      a3[k][q] = {a3x[k][q], ur * gt - ut * gr};
+    }
+  FF::template run<RPB>(a, o, bufa, bufb, W, t, f);
   store_pair(2, 3);
   FF::template run<RPB>(a3, o, bufa, bufb, W, t, f);
   // separate the packed real fields: X(n) = (G(n) + conj G(-n))/2, Y(n) = (G(n) - conj G(-n))/(2i)
@@ -842,7 +826,8 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
-    const C2<T>* src = inter + ((int64_t)(pl * io.nf_plane + fld) * L) * d.mt + n;
+    const int sf = io.use_map ? io.src_field[fld] : fld;
+    const C2<T>* src = inter + ((int64_t)(pl * io.nf_plane + sf) * L) * d.mt + n;
 #pragma unroll
     for (int k = 0; k < FF::PER0; ++k)
 #pragma unroll
@@ -875,26 +860,11 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
       if (t == 0) dst[(int64_t)h * d.mt] = cd{0.0, 0.0};
     }
   };
-  if constexpr (Z::PREFETCH) {
-    typename FF::In cur, nxt;
-    TileWalk tw(ntiles);
-    if (tw.first < tw.last) load(tw.first, cur);
-    for (int id = tw.first; id < tw.last; id += tw.per_group) {
-      const int idn = id + tw.per_group;
-      if (idn < tw.last) load(idn, nxt);
-      transform_store(id, cur);
-#pragma unroll
-      for (int k = 0; k < FF::PER0; ++k)
-#pragma unroll
-        for (int q = 0; q < FF::R0; ++q) cur[k][q] = nxt[k][q];
-    }
-  } else {
-    const int id = single_tile(ntiles);
-    if (id < 0) return;  // padding workgroup (uniform over the workgroup)
-    typename FF::In cur;
-    load(id, cur);
-    transform_store(id, cur);
-  }
+  const int id = single_tile(ntiles);
+  if (id < 0) return;  // padding workgroup (uniform over the workgroup)
+  typename FF::In cur;
+  load(id, cur);
+  transform_store(id, cur);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -919,12 +889,9 @@ size_t inter_bytes_per_plane(const tc_ctx* c) {
   return (size_t)inter_fields(c) * c->d.pz * c->d.mt * el;
 }
 
-// Workgroups of a z kernel: with prefetching a few per CU (256 CUs), each
-// walking many tiles; without, one per tile.
-static unsigned z_blocks(int64_t ntiles, bool prefetch) {
-  if (prefetch) return (unsigned)(ntiles < 256 * 8 ? ntiles : 256 * 8);
-  return (unsigned)(8 * ((ntiles + 7) / 8));  // see single_tile
-}
+// Workgroups of a z kernel: one per tile, padded to a multiple of 8 (see
+// single_tile).
+static unsigned z_blocks(int64_t ntiles) { return (unsigned)(8 * ((ntiles + 7) / 8)); }
 
 template <typename T, int L>
 static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const ZIo& io, void* inter, const C2<T>* W) {
@@ -937,7 +904,7 @@ static hipError_t run_zinv(tc_ctx* c, int plane0, int np, const ZIo& io, void* i
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles, Z::PREFETCH);
+  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles);
   hipLaunchKernelGGL((k_zinv<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, io,
                      reinterpret_cast<C2<T>*>(inter), W);
   return hipGetLastError();
@@ -971,7 +938,7 @@ static hipError_t run_zfwd(tc_ctx* c, int plane0, int np, const ZIo& io, const v
     attr = true;
   }
   const int tiles = (c->d.mt + Z::NF - 1) / Z::NF;
-  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles, Z::PREFETCH);
+  const unsigned blocks = z_blocks((int64_t)np * io.nfields * tiles);
   hipLaunchKernelGGL((k_zfwd<T, L>), dim3(blocks), dim3(Z::NF * Z::TPF), lds, c->stream, c->d, plane0, np, io,
                      reinterpret_cast<const C2<T>*>(inter), W);
   return hipGetLastError();
@@ -1032,6 +999,12 @@ static hipError_t run_theta_adj(tc_ctx* c, int np, void* inter) {
   hipLaunchKernelGGL((k_theta_adj<double, L>), dim3(blocks), dim3(TS::TPF * TS::RPB), lds, c->stream, c->d, np,
                      reinterpret_cast<cd*>(inter), c->tw_t);
   return hipGetLastError();
+}
+
+void adjoint_field_map(ZIo& zo) {
+  const int where[6] = {6, 7, 2, 3, 4, 5};
+  zo.use_map = 1;
+  for (int k = 0; k < 6; ++k) zo.src_field[k] = where[k];
 }
 
 hipError_t launch_theta_adj(tc_ctx* c, int np, void* inter) {

@@ -159,3 +159,4 @@ def test_adjoint_step_at_scale_dot_product():
     finally:
         S.close()
         torch.cuda.empty_cache()
+
