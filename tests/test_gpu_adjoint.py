@@ -160,3 +160,44 @@ def test_adjoint_step_at_scale_dot_product():
         S.close()
         torch.cuda.empty_cache()
 
+
+def _read_adjoint_reference():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint_reference.txt")
+    scalars, samples = {}, []
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if "=" in line:
+            k, v = (x.strip() for x in line.split("="))
+            scalars[k] = float(v)
+        else:
+            c, j, s, n, re, im = line.split()
+            samples.append((int(c), int(j), int(s), int(n), complex(float(re), float(im))))
+    return scalars, samples
+
+
+def test_differentiation_workload_gradient_vs_oracle_reference():
+    """The gradient of the differentiation workload (T = 400 steps,
+    checkpoints every 20) against the FP64 oracle's checkpointed adjoint,
+    stored by tests/golden/make_adjoint_reference.py: J, the projections on
+    the 8 directions of the finite-difference check, |g| and 256 sampled
+    coefficients."""
+    from paper_1311_2481_amd.autograd import final_energy_and_gradient
+    ref, samples = _read_adjoint_reference()
+    S, P, cfg = make_pair("adjoint")
+    u0 = tc_inputs.initial_state(P.r, cfg)
+    base = dg.couette_state(P)
+    J, g = final_energy_and_gradient(S, to_dev(base), to_dev(u0 - base), cfg.steps, every=cfg.checkpoint_every)
+    g = to_host(g)
+    eJ = abs(J - ref["J"]) / abs(ref["J"])
+    gn = np.sqrt(adj.inner(g, g))
+    en = abs(gn - ref["grad_norm"]) / ref["grad_norm"]
+    ep = max(abs(adj.inner(g, tc_inputs.random_direction(P.r, cfg, k)) - ref[f"proj_{k}"]) / abs(ref[f"proj_{k}"])
+             for k in range(1000, 1008))
+    es = max(abs(g[c, j, s, n] - v) for c, j, s, n, v in samples) / ref["grad_norm"]
+    print(f"gradient vs oracle reference (T = {cfg.steps}): J rel {eJ:.2e}, |g| rel {en:.2e}, "
+          f"projections rel max {ep:.2e}, sampled coefficients max / |g| {es:.2e}")
+    assert eJ < 1e-10 and en < 1e-9 and ep < 1e-9 and es < 1e-10
+    S.close()
