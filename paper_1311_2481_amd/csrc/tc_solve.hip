@@ -20,6 +20,14 @@
 // No pivoting: the Neumann rows of P are rescaled to the size of the
 // neighbouring Laplacian rows, and the factorisation reports any zero or
 // non-finite pivot.
+//
+// On large grids the first sweeps (P's forward sweeps in k_pc1 and k_pc3,
+// the Helmholtz operators' in k_pc2) rebuild their multipliers row by row
+// from the operator rows instead of loading them: the elimination that
+// k_factor runs, in the same order and without contraction, so the values
+// are the stored ones bit for bit.  Only the second-sweep coefficients,
+// which the elimination produces in the opposite row order, come from
+// memory.
 #include "tc_internal.h"
 
 namespace tc {
@@ -60,7 +68,11 @@ __device__ __forceinline__ const double* facp(const double* fac, const Dims& d, 
 
 // ------------------------------------------------------------------ factor
 // Row j of operator op in natural column order: entry k multiplies node j+k-4.
-__device__ void operator_row(const double* rc, const Dims& d, int op, int j, double a, double b, double* row) {
+// Evaluated without contraction, like the elimination below, so that the
+// sweeps that rebuild factors on the fly reproduce the stored ones exactly.
+__device__ __forceinline__ void operator_row(const double* rc, const Dims& d, int op, int j, double a, double b,
+                                             double* row) {
+#pragma clang fp contract(off)
   const double* R = rc + (int64_t)j * RC_N;
   const int M = d.n_r - 1;
   const bool wall = (j == 0 || j == M);
@@ -86,6 +98,51 @@ __device__ void operator_row(const double* rc, const Dims& d, int op, int j, dou
   row[HW] += diag;
 }
 
+// Running factorization of one operator in its processing order (ascending
+// rows for P, descending for the Helmholtz operators): U[q] is the U-row
+// (pivot and the 4 entries after it) of the row q+1 places earlier.
+struct Elim {
+  double U[4][5];
+  __device__ __forceinline__ void reset() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[q][c] = 0.0;
+  }
+  // Next row: ip = its place in processing order, row its entries in
+  // processing column order (entry HW on the diagonal).  Gives the
+  // multipliers of the 4 previous rows (mult[q-1]: the row q places
+  // earlier) and leaves the row's U-row in row[HW .. HW+4] and in U[0].
+  __device__ __forceinline__ void next(double (&row)[NB9], int ip, double (&mult)[4]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int q = 4; q >= 1; --q) {
+      double m = 0.0;
+      if (ip - q >= 0) {
+        m = row[HW - q] / U[q - 1][0];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) row[HW - q + c] -= m * U[q - 1][c];
+      }
+      mult[q - 1] = m;
+    }
+#pragma unroll
+    for (int q = 3; q >= 1; --q)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[q][c] = U[q - 1][c];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) U[0][c] = row[HW + c];
+  }
+  // multipliers of row j of operator op (processing place ip)
+  __device__ __forceinline__ void row_mult(const double* rc, const Dims& d, int op, int j, int ip, double a, double b,
+                                           double (&mult)[4]) {
+    double nat[NB9], row[NB9];
+    operator_row(rc, d, op, j, a, b, nat);
+#pragma unroll
+    for (int c = 0; c < NB9; ++c) row[c] = (op != OP_P) ? nat[NB9 - 1 - c] : nat[c];
+    next(row, ip, mult);
+  }
+};
+
 __global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac, Dims d, int* bad) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= NOPS * d.ndm) return;
@@ -94,32 +151,21 @@ __global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac
   const double a = n * d.kt, b = labs * d.kz;
   const bool rev = (op != OP_P);
   const int M = d.n_r - 1;
-  double U[4][5];  // U[q]: U-row of the row q+1 places earlier in processing order
-  for (int q = 0; q < 4; ++q)
-    for (int c = 0; c < 5; ++c) U[q][c] = 0.0;
+  Elim E;
+  E.reset();
   int flag = 0;
   for (int ip = 0; ip <= M; ++ip) {
     const int j = rev ? M - ip : ip;
-    double nat[NB9], row[NB9];
+    double nat[NB9], row[NB9], mult[4];
     operator_row(rc, d, op, j, a, b, nat);
     for (int c = 0; c < NB9; ++c) row[c] = rev ? nat[NB9 - 1 - c] : nat[c];
+    E.next(row, ip, mult);
     double* F = const_cast<double*>(facp(fac, d, op, j)) + dm;
-    // eliminate the columns of the 4 previous rows, oldest first
-    for (int q = 4; q >= 1; --q) {
-      double m = 0.0;
-      if (ip - q >= 0) {
-        m = row[HW - q] / U[q - 1][0];
-        for (int c = 0; c < 5; ++c) row[HW - q + c] -= m * U[q - 1][c];
-      }
-      F[(int64_t)(q - 1) * d.ndm] = m;
-    }
+    for (int q = 0; q < 4; ++q) F[(int64_t)q * d.ndm] = mult[q];
     const double piv = row[HW];
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) flag = 1;
     F[(int64_t)4 * d.ndm] = 1.0 / piv;
     for (int c = 1; c <= 4; ++c) F[(int64_t)(4 + c) * d.ndm] = (ip + c <= M) ? row[HW + c] : 0.0;
-    for (int q = 3; q >= 1; --q)
-      for (int c = 0; c < 5; ++c) U[q][c] = U[q - 1][c];
-    for (int c = 0; c < 5; ++c) U[0][c] = row[HW + c];
   }
   if (flag) atomicOr(bad, 1);
 }
@@ -340,10 +386,20 @@ __global__ __launch_bounds__(64) void k_pc1(TC_PC_ARGS) {
       pv[c] = Np[c * F + o];
     }
   };
+  // multipliers of P's forward sweep: rebuilt row by row in ascending order
+  // by the one-row kernels (large grids, where the sweep streams at HBM
+  // speed and the arithmetic is free), loaded by the chunked ones (small
+  // grids, where the sweep is a latency chain that the arithmetic lengthens)
+  Elim EP;
+  EP.reset();
   auto load_fac = [&](int i, double (&fl)[4]) {
-    const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+    if constexpr (CH == 1) {
+      EP.row_mult(rc, d, OP_P, i, i, a, L.b, fl);
+    } else {
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+      for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+    }
   };
   // row j enters: Ne = 2 N^i - N^{i-1} (kept in N_prev), wall terms, D1 scatter
   auto feed = [&](int j, const cd (&nv)[3], const cd (&pv)[3]) {
@@ -472,6 +528,12 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
     for (int c = 0; c < 5; ++c) fu[c] = Fp[(int64_t)(4 + c) * d.ndm];
     y = p[jj * S + L.o];
   };
+  // multipliers of the Helmholtz operators' first sweeps: rebuilt row by
+  // row in descending order by the one-row kernels, loaded by the chunked
+  // ones (as for P in k_pc1)
+  Elim EH[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) EH[c].reset();
   auto load_h = [&](int i, cd (&ne)[3], cd (&uu)[3], cd (&uq)[3], double (&fh)[3][4]) {
     const int64_t o = i * S + L.o;
 #pragma unroll
@@ -479,9 +541,13 @@ __global__ __launch_bounds__(64) void k_pc2(TC_PC_ARGS) {
       ne[c] = Np[c * F + o];
       uu[c] = u[c * F + o];
       uq[c] = up[c * F + o];
-      const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
+      if constexpr (CH == 1) {
+        EH[c].row_mult(rc, d, OP_HP + c, i, M - i, a, L.b, fh[c]);
+      } else {
+        const double* Fh = facp(fac, d, OP_HP + c, i) + L.dm;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fh[c][q] = Fh[(int64_t)q * d.ndm];
+        for (int q = 0; q < 4; ++q) fh[c][q] = Fh[(int64_t)q * d.ndm];
+      }
     }
   };
   // back-substitution of p* at row jj
@@ -605,10 +671,20 @@ __global__ __launch_bounds__(64) void k_pc3(TC_PC_ARGS) {
       zv[c] = un[c * F + j * S + L.o];
     }
   };
+  // multipliers of P's forward sweep: rebuilt row by row in ascending order
+  // by the one-row kernels (large grids, where the sweep streams at HBM
+  // speed and the arithmetic is free), loaded by the chunked ones (small
+  // grids, where the sweep is a latency chain that the arithmetic lengthens)
+  Elim EP;
+  EP.reset();
   auto load_fac = [&](int i, double (&fl)[4]) {
-    const double* Fp = facp(fac, d, OP_P, i) + L.dm;
+    if constexpr (CH == 1) {
+      EP.row_mult(rc, d, OP_P, i, i, a, L.b, fl);
+    } else {
+      const double* Fp = facp(fac, d, OP_P, i) + L.dm;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+      for (int q = 0; q < 4; ++q) fl[q] = Fp[(int64_t)q * d.ndm];
+    }
   };
   // row j: u* by the second Helmholtz sweep, then its divergence scattered
   auto feed = [&](int j, const cd (&zv)[3], const double (&fh)[3][5]) {
