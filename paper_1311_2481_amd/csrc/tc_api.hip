@@ -140,7 +140,7 @@ void twiddles(int L, std::vector<C2<T>>& out) {
 
 void free_ctx(tc_ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->rc_dev, c->fac, c->tw_t, c->tw_z, c->twf_t, c->twf_z, c->u, c->u_prev, c->N_prev,
+  void* ptrs[] = {c->rc_dev, c->fac, c->flin, c->tw_t, c->tw_z, c->twf_t, c->twf_z, c->u, c->u_prev, c->N_prev,
                   c->N_cur, c->p, c->omega, c->aux, c->inter, c->zmax, c->diag_wr, c->diag_uc, c->red};
   for (void* p : ptrs) dev_free(p);
   for (auto& t : c->timers)
@@ -644,6 +644,13 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   const size_t FB = field_bytes(c);
   c->rc_dev = dev_alloc<double>(c, c->rc.size() * sizeof(double), st);
   c->fac = dev_alloc<double>(c, (size_t)NOPS * d.n_r * NFAC * d.ndm * sizeof(double), st);
+  // the line predictor-corrector where the grid allows it (TC_PC_LINE=0
+  // selects the four-sweep kernels instead)
+  {
+    const char* e = std::getenv("TC_PC_LINE");
+    if (line_lps(d) > 0 && !(e && std::atoi(e) == 0))
+      c->flin = dev_alloc<double>(c, (size_t)NOPS * d.n_r * NFAC * d.ndm * sizeof(double), st);
+  }
   c->tw_t = dev_alloc<cd>(c, (size_t)d.pt * sizeof(cd), st);
   c->tw_z = dev_alloc<cd>(c, (size_t)d.pz * sizeof(cd), st);
   c->twf_t = dev_alloc<cf>(c, (size_t)d.pt * sizeof(cf), st);

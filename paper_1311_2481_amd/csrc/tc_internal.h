@@ -33,6 +33,19 @@ constexpr int RC_R = 0, RC_IR = 1, RC_IR2 = 2, RC_W1 = 3, RC_W2 = 12, RC_N = 21;
 constexpr int NOPS = 4, NFAC = 9;
 enum { OP_P = 0, OP_HP = 1, OP_HM = 2, OP_HZ = 3 };
 
+// Predictor-corrector with the radial lines on chip (tc_line.hip), for
+// grids of n_r = LINE_RPL * LPS radial nodes with LPS ("lanes per slot") a
+// power of two: lane k of a slot's LPS lanes holds rows LINE_RPL k ..
+// LINE_RPL k + LINE_RPL - 1.  Its factors (flin) hold the values of fac
+// lane-contiguously: for operator op, distinct mode dm and lane k, LINE_Q
+// pairs of doubles, pair q at
+//   flin[((op * ndm + dm) * LINE_Q + q) * 2 LPS + 2 k + {0, 1}];
+// counting the lane's doubles e = 0 .. 2 LINE_Q - 1 in pair order, e < 32
+// is first-sweep multiplier c = e % 4 of row LINE_RPL k + e / 4, and
+// e = 32 + 5 r + c is the inverse pivot (c = 0) or second-sweep
+// coefficient c (c = 1..4) of row LINE_RPL k + r.
+constexpr int LINE_RPL = 8, LINE_Q1 = 16, LINE_Q = 36;
+
 // Doubles of the static scratch array of tc_get_diag_noalloc (4 MiB per GPU).
 constexpr size_t TC_DIAG_SCRATCH_DOUBLES = (size_t)1 << 19;
 
@@ -92,6 +105,7 @@ struct tc_ctx {
   // device data owned by the context
   double* rc_dev = nullptr;
   double* fac = nullptr;
+  double* flin = nullptr;    // lane-contiguous copy of fac (line predictor-corrector only)
   tc::cd* tw_t = nullptr;   // exp(-2 pi i e / p_theta)
   tc::cd* tw_z = nullptr;   // exp(-2 pi i e / p_z)
   tc::cf* twf_t = nullptr;
@@ -128,6 +142,7 @@ tc_status fail(tc_ctx* c, tc_status s, const std::string& msg);
 tc_status hip_check(tc_ctx* c, hipError_t e, const char* what);
 
 // launchers (return hipError_t from hipGetLastError)
+// (also fills c->flin when it is allocated)
 hipError_t launch_factor(tc_ctx* c, int* bad_dev);
 // componentwise backward error of the stored factors on one solve per
 // operator and mode (tmp: n_r * 4 * ndm doubles of work space)
@@ -143,6 +158,12 @@ hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x);
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev_scratch,
                      cd* u_next, cd* p, int want_p, cd* omega_out);
 bool pc_fuses_curl(const tc_ctx* c);
+// the line predictor-corrector (tc_line.hip): its lanes per slot on this
+// grid (0 where it does not run), and its launch (the arguments of
+// launch_pc; omg NULL: no curl)
+int line_lps(const Dims& d);
+hipError_t launch_pc_line(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, const cd* N_prev, cd* u_next,
+                          cd* p, int want_p, cd* omg);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

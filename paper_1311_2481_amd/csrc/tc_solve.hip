@@ -143,7 +143,8 @@ struct Elim {
   }
 };
 
-__global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac, Dims d, int* bad) {
+__global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac, double* __restrict__ flin, Dims d,
+                         int* bad) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= NOPS * d.ndm) return;
   const int op = gid / d.ndm, dm = gid - op * d.ndm;
@@ -164,15 +165,26 @@ __global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac
     for (int q = 0; q < 4; ++q) F[(int64_t)q * d.ndm] = mult[q];
     const double piv = row[HW];
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) flag = 1;
-    F[(int64_t)4 * d.ndm] = 1.0 / piv;
-    for (int c = 1; c <= 4; ++c) F[(int64_t)(4 + c) * d.ndm] = (ip + c <= M) ? row[HW + c] : 0.0;
+    double sec[5];  // inverse pivot, second-sweep coefficients
+    sec[0] = 1.0 / piv;
+    for (int c = 1; c <= 4; ++c) sec[c] = (ip + c <= M) ? row[HW + c] : 0.0;
+    for (int c = 0; c <= 4; ++c) F[(int64_t)(4 + c) * d.ndm] = sec[c];
+    if (flin) {
+      // the same values in the line kernel's lane-contiguous layout
+      const int lps = d.n_r / LINE_RPL, k = j / LINE_RPL, r = j % LINE_RPL;
+      double* Lp = flin + ((int64_t)op * d.ndm + dm) * LINE_Q * 2 * lps + 2 * k;
+      auto put = [&](int e, double x) { Lp[(int64_t)(e / 2) * 2 * lps + (e % 2)] = x; };
+      for (int q = 0; q < 4; ++q) put(4 * r + q, mult[q]);
+      for (int c = 0; c <= 4; ++c) put(4 * LINE_RPL + 5 * r + c, sec[c]);
+    }
   }
   if (flag) atomicOr(bad, 1);
 }
 
 hipError_t launch_factor(tc_ctx* c, int* bad_dev) {
   const int total = NOPS * c->d.ndm;
-  hipLaunchKernelGGL(k_factor, dim3((total + 63) / 64), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->d, bad_dev);
+  hipLaunchKernelGGL(k_factor, dim3((total + 63) / 64), dim3(64), 0, c->stream, c->rc_dev, c->fac, c->flin, c->d,
+                     bad_dev);
   return hipGetLastError();
 }
 
@@ -1062,14 +1074,18 @@ hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
 // saturates HBM on large grids) down.
 static bool pc_chunked(const tc_ctx* c) { return (c->d.ndm + 31) / 32 < 2 * 4 * 256; }
 
-// (only the rotational form transforms the curl)
-bool pc_fuses_curl(const tc_ctx* c) { return TC_FUSE_CURL && !pc_chunked(c) && c->d.form == TC_ROTATIONAL; }
+// (only the rotational form transforms the curl; the line kernel forms it
+// on every grid it takes)
+bool pc_fuses_curl(const tc_ctx* c) {
+  return TC_FUSE_CURL && c->d.form == TC_ROTATIONAL && (c->flin || !pc_chunked(c));
+}
 
 hipError_t launch_pc(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, cd* N_prev, cd* u_next, cd* p,
                      int want_p, cd* omega_out) {
+  cd* omg = pc_fuses_curl(c) ? omega_out : nullptr;
+  if (c->flin) return launch_pc_line(c, u, u_prev, N, N_prev, u_next, p, want_p, omg);
   const int blocks = (c->d.ndm + 31) / 32;
   const bool chunked = pc_chunked(c);
-  cd* omg = pc_fuses_curl(c) ? omega_out : nullptr;
   using K = void (*)(TC_PC_ARGS);
   const K ks[2][4] = {{k_pc1<1>, k_pc2<1>, k_pc3<1>, k_pc4<1>},
                       {k_pc1<PC_CH>, k_pc2<PC_CH>, k_pc3<PC_CH>, k_pc4<PC_CH>}};

@@ -1,0 +1,92 @@
+"""The line predictor-corrector (each mode's radial line spread over 4, 8 or
+16 lanes and held on chip; grids of 32, 64 and 128 radial nodes) against the
+FP64 oracle, and against the four-sweep kernels on the same inputs (a
+context created with TC_PC_LINE=0 uses those)."""
+import numpy as np
+import pytest
+
+import oracle
+import tc_inputs
+from oracle import scheme
+from gpu_common import floor_tol, make_pair, rel_l2, to_dev, to_host, twin_floor
+
+pytestmark = pytest.mark.gpu
+
+# (workload, overrides): 4, 8 and 16 lanes per slot; the (12, 20) shapes
+# leave a ragged last tile and waves whose slots straddle two |l|.
+CASES = [
+    ("small", {}),
+    ("medium", {}),
+    ("medium", dict(m_theta=12, m_z=20)),
+    ("medium", dict(n_r=128, m_theta=12, m_z=20)),
+]
+IDS = ["nr32", "nr64", "nr64-ragged", "nr128-ragged"]
+
+
+def _inputs(P, cfg, seed):
+    """u^i, u^{i-1} and N^{i-1} that differ from one another, so that every
+    input of the step enters the result."""
+    shape = (3, cfg.n_r, cfg.m_z, cfg.m_theta)
+    u0 = tc_inputs.initial_state(P.r, cfg)
+    up = u0 + 1e-3 * tc_inputs.random_state(shape, seed)
+    up[:, 0] = u0[:, 0]
+    up[:, -1] = u0[:, -1]
+    Np = oracle.nonlinear_rot(P, u0) + 0.1 * tc_inputs.random_state(shape, seed + 1)
+    return u0, up, Np
+
+
+def _pair(case, monkeypatch, line=True, **extra):
+    name, over = case
+    if not line:
+        monkeypatch.setenv("TC_PC_LINE", "0")
+    try:
+        return make_pair(name, **over, **extra)
+    finally:
+        monkeypatch.delenv("TC_PC_LINE", raising=False)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_line_step_matches_oracle(case, dt, monkeypatch):
+    S, P, cfg = _pair(case, monkeypatch, dt=dt)
+    u0, up, Np = _inputs(P, cfg, 71)
+    S.set_state(to_dev(u0), to_dev(up), to_dev(Np))
+    S.step(1)
+    ug, pg = (to_host(x) for x in S.get_state())
+    ur, pr, Nr = scheme.step(P, u0, up, Np)
+    eu, ep = rel_l2(ug, ur), rel_l2(pg, pr)
+    fu = twin_floor(P, lambda Q: scheme.step(Q, u0, up, Np)[0], ur)
+    fp = twin_floor(P, lambda Q: scheme.step(Q, u0, up, Np)[1], pr)
+    print(f"line step {case} dt={dt:g}: u rel_l2 {eu:.2e} (floor {fu:.2e}), p {ep:.2e} (floor {fp:.2e})")
+    assert eu <= floor_tol(fu) and ep <= floor_tol(fp)
+    # the Nyquist slot stays empty
+    assert np.abs(ug[:, :, cfg.m_z // 2]).max() == 0.0 and np.abs(pg[:, cfg.m_z // 2]).max() == 0.0
+    S.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_line_matches_four_sweep_kernels(case, monkeypatch):
+    """Five steps of both predictor-corrector forms from the same state: the
+    states, pressures and histories agree within the one-step rounding floor
+    times the number of steps; the line context holds the second factor copy."""
+    S, P, cfg = _pair(case, monkeypatch, dt=1e-5)
+    R, _, _ = _pair(case, monkeypatch, line=False, dt=1e-5)
+    assert S.memory_bytes() > R.memory_bytes()
+    u0, up, Np = _inputs(P, cfg, 81)
+    fu = twin_floor(P, lambda Q: scheme.step(Q, u0, up, Np)[0], scheme.step(P, u0, up, Np)[0])
+    for X in (S, R):
+        X.set_state(to_dev(u0), to_dev(up), to_dev(Np))
+    worst = 0.0
+    for k in range(1, 6):
+        for X in (S, R):
+            X.step(1)
+        (ua, pa), (ub, pb) = ([to_host(x) for x in X.get_state()] for X in (S, R))
+        (ha, na), (hb, nb) = ([to_host(x) for x in X.get_history()] for X in (S, R))
+        errs = [rel_l2(ua, ub), rel_l2(pa, pb), rel_l2(ha, hb), rel_l2(na, nb)]
+        worst = max(worst, max(errs) / k)
+        print(f"step {k}: line vs four-sweep rel_l2 u {errs[0]:.2e}, p {errs[1]:.2e}, "
+              f"u_prev {errs[2]:.2e}, N_prev {errs[3]:.2e}")
+        assert max(errs) <= k * floor_tol(fu)
+    print(f"one-step floor {fu:.2e}; worst difference per step {worst:.2e}")
+    S.close()
+    R.close()
