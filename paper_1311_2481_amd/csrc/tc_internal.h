@@ -164,6 +164,8 @@ bool pc_fuses_curl(const tc_ctx* c);
 int line_lps(const Dims& d);
 hipError_t launch_pc_line(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, const cd* N_prev, cd* u_next,
                           cd* p, int want_p, cd* omg);
+// transposed solves on the line layout (the arguments of launch_solve_t)
+hipError_t launch_solve_t_line(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

@@ -482,6 +482,105 @@ __global__ __launch_bounds__(WAVES * NLANE) void k_pcl(const double* __restrict_
   }
 }
 
+// Transposed solves A^T x = rhs on the same line layout (the adjoint
+// step's P and Helmholtz solves), A = S^-1 L U in the factor's row order
+// (S: the Neumann row scale of P, identity for the Helmholtz operators):
+//   U^T w = rhs   w_i = (rhs_i - sum_c U(i-c, i) w_{i-c}) / U(i, i)
+//   L^T v = w     v_i = w_i - sum_q L(i+1+q, i) v_{i+1+q}
+//   x = S v
+// in the operator's processing order i.  The coefficients of row i come from
+// the 4 rows before it (U^T) or after it (L^T) in that order, so each lane
+// takes 4 rows of U coefficients from one neighbour and 4 rows of
+// multipliers from the other by shuffles.  Operators op0 .. op0 + nop - 1 on
+// fields rhs + k F -> x + k F (x may alias rhs: each lane reads its rows
+// before it writes them).
+template <int LPS, bool LU>
+__device__ __forceinline__ void line_solve_t(const double* fl, cd (&f)[RPL], int lane, int ch) {
+  double m[RPL][4], uc[RPL][4], ip[RPL];
+  load_first<LPS>(fl, m);
+  load_second<LPS>(fl, ip, uc);
+  // neighbours' rows: the lane before (rows 4..7 of its slot) and after
+  // (rows 0..3), zero past the ends of the line
+  const int prev = (lane - 1) & (NLANE - 1), next = (lane + 1) & (NLANE - 1);
+  double ua[HW][4], mb[HW][4];  // U rows feeding U^T, multiplier rows feeding L^T
+#pragma unroll
+  for (int i = 0; i < HW; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      // LU (ascending rows): U^T needs the rows before (lane - 1's rows 4..7),
+      // L^T the rows after (lane + 1's rows 0..3); UL the other way round
+      const double a = __shfl(uc[LU ? RPL - HW + i : i][c], LU ? prev : next, NLANE);
+      const double b = __shfl(m[LU ? i : RPL - HW + i][c], LU ? next : prev, NLANE);
+      ua[i][c] = (LU ? ch == 0 : ch == LPS - 1) ? 0.0 : a;
+      mb[i][c] = (LU ? ch == LPS - 1 : ch == 0) ? 0.0 : b;
+    }
+  // coefficient of the c-th previous output, by row, for each recurrence
+  double ca[RPL][4], cb[RPL][4];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      // U^T: row r's coefficient c is U(row i-1-c, entry c+1), i the
+      // processing place of row r (rows r-1-c for LU, r+1+c for UL)
+      const int ra = LU ? r - 1 - c : r + 1 + c;
+      ca[r][c] = (ra >= 0 && ra < RPL) ? uc[ra][c] : ua[LU ? ra + HW : ra - RPL][c];
+      // L^T: multiplier c of row i+1+c (rows r+1+c for LU, r-1-c for UL)
+      const int rb = LU ? r + 1 + c : r - 1 - c;
+      cb[r][c] = (rb >= 0 && rb < RPL) ? m[rb][c] : mb[LU ? rb - RPL : rb + HW][c];
+    }
+  line_solve<LPS, LU, true>(ca, ip, f, lane, ch);
+  line_solve<LPS, !LU, false>(cb, ip, f, lane, ch);
+}
+
+template <int LPS>
+__global__ __launch_bounds__(WAVES * NLANE) void k_solve_tl(const double* __restrict__ flin, Dims d, int op0, int nop,
+                                                           const cd* rhs, cd* x, int ntile, int per) {
+  constexpr int SPW = NLANE / LPS;
+  const int lane = threadIdx.x % NLANE, wv = threadIdx.x / NLANE;
+  const int seg = lane / LPS, ch = lane % LPS;
+  const int xcd = blockIdx.x % 8, rr = blockIdx.x / 8;
+  const int t = xcd * per + rr / 8, q = rr % 8;
+  if (t >= ntile) return;
+  const int sign = q & 1;
+  const int dm = ((t * 4 + (q >> 1)) * WAVES + wv) * SPW + seg;
+  const bool active = dm < d.ndm;
+  if (__ballot(active) == 0) return;
+  const int dmc = active ? dm : d.ndm - 1;
+  const int labs = dmc / d.mt, n = dmc - labs * d.mt;
+  const bool nyq = active && sign == 1 && labs == 0;
+  const bool reg = active && !nyq;
+  const int M = d.n_r - 1;
+  const int64_t F = d.F, S = d.S;
+  const int j0 = RPL * ch;
+  const int s = sign ? d.mz - labs : labs;
+  const int64_t o = reg ? (int64_t)s * d.mt + n : 0;
+  const int64_t onyq = (int64_t)d.nyq * d.mt + n;
+  const bool zero_mode = labs == 0 && n == 0;
+  const double* fl = flin + (int64_t)dmc * LINE_Q * 2 * LPS + 2 * ch;
+  const int64_t fop = (int64_t)d.ndm * LINE_Q * 2 * LPS;
+#pragma unroll 1
+  for (int k = 0; k < nop; ++k) {
+    const int op = op0 + k;
+    cd f[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) f[r] = rhs[k * F + (int64_t)(j0 + r) * S + o];
+    if (op == OP_P) line_solve_t<LPS, true>(fl + op * fop, f, lane, ch);
+    else line_solve_t<LPS, false>(fl + op * fop, f, lane, ch);
+    if (op == OP_P) {
+      // x = S v: the Neumann rows 0 and M (row M of mode (0,0) is Dirichlet)
+      if (ch == 0) f[0] = scl(f[0], d.s0);
+      if (ch == LPS - 1 && !zero_mode) f[RPL - 1] = scl(f[RPL - 1], d.sM);
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int64_t oj = k * F + (int64_t)(j0 + r) * S;
+      if (reg) x[oj + o] = f[r];
+      if (nyq) x[oj + onyq] = z0();
+    }
+  }
+  (void)M;
+}
+
 // Lanes per slot where the line kernel runs: n_r = 8 LPS with LPS = 4, 8
 // or 16.  Longer lines need 32 or 64 lanes per slot, whose loads touch as
 // many cache lines per instruction; there the four-sweep kernels, which
@@ -507,6 +606,26 @@ static hipError_t launch_lps(tc_ctx* c, const cd* u, const cd* u_prev, const cd*
     hipLaunchKernelGGL((k_pcl<LPS, false>), grid, block, 0, c->stream, c->rc_dev, c->flin, d, u, u_prev, N, N_prev,
                        u_next, p, want_p, omg, ntile, per);
   return hipGetLastError();
+}
+
+template <int LPS>
+static hipError_t launch_solve_t_lps(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
+  const Dims& d = c->d;
+  constexpr int SPW = NLANE / LPS;
+  const int ntile = (d.ndm + 16 * SPW - 1) / (16 * SPW);
+  const int per = (ntile + 7) / 8;
+  hipLaunchKernelGGL((k_solve_tl<LPS>), dim3(64 * per), dim3(WAVES * NLANE), 0, c->stream, c->flin, d, op0, nop, rhs,
+                     x, ntile, per);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_t_line(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
+  switch (line_lps(c->d)) {
+    case 4: return launch_solve_t_lps<4>(c, op0, nop, rhs, x);
+    case 8: return launch_solve_t_lps<8>(c, op0, nop, rhs, x);
+    case 16: return launch_solve_t_lps<16>(c, op0, nop, rhs, x);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_pc_line(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N, const cd* N_prev, cd* u_next,

@@ -1058,6 +1058,7 @@ __global__ __launch_bounds__(64) void k_solve_tn(const double* __restrict__ fac,
 }
 
 hipError_t launch_solve_t(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x) {
+  if (c->flin && (nop == 1 || (nop == 3 && op0 == OP_HP))) return launch_solve_t_line(c, op0, nop, rhs, x);
   const int blocks = (c->d.ndm + 31) / 32;
   if (nop == 1)
     hipLaunchKernelGGL((k_solve_tn<1, 8>), dim3(blocks), dim3(64), 0, c->stream, c->fac, c->d, op0, rhs, x);
