@@ -151,8 +151,8 @@ class Solver:
         self._check(self.lib.tc_set_state(self.ctx, self._arr(u, 3, "u"), self._arr(u_prev, 3, "u_prev"),
                                           self._arr(N_prev, 3, "N_prev")))
 
-    def get_state(self, with_pressure=True):
-        u = self.empty(3)
+    def get_state(self, with_pressure=True, out=None):
+        u = self.empty(3) if out is None else out
         p = self.empty(1) if with_pressure else None
         self._check(self.lib.tc_get_state(self.ctx, self._arr(u, 3, "u"), self._arr(p, 1, "p")))
         return (u, p) if with_pressure else u

@@ -37,27 +37,32 @@ class TCSteps(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         S = ctx.solver
-        ub = S.adjoint_seed(ctx.uT, float(gJ))
-        upb = torch.zeros_like(ub)
-        Nb = torch.zeros_like(ub)
-        adj_in = S.empty(9)
+        # cotangents of (u^{k+1}, u^k, N^k) in one 9-field buffer; two such
+        # buffers in turn take the input and the output of each adjoint step
+        bufs = [S.zeros(9), S.empty(9)]
+        S.adjoint_seed(ctx.uT, float(gJ), out=bufs[0][0:3])
+        cur = 0
+        # one segment's velocities, newest first: fields 3m .. 3m+2 hold
+        # u^{end-1-m}, so the inputs (u^k, u^{k-1}) of step k are the six
+        # fields from 3 (end-1-k) on, with no copy
+        seg = S.empty(3 * (ctx.every + 1))
         for start, cu, cup, cNp in reversed(ctx.checkpoints):
             end = min(start + ctx.every, ctx.nsteps)
-            # recompute the segment: inputs (u^k, u^{k-1}) of every step in it
+            n = end - start
+            # recompute the segment from its checkpoint
             S.set_state(cu, cup, cNp)
-            inputs = [(cu, cup)]
-            for _ in range(start, end - 1):
+            seg[3 * n:3 * n + 3].copy_(cup)
+            seg[3 * (n - 1):3 * n].copy_(cu)
+            for k in range(start + 1, end):
                 S.step(1)
-                u = S.get_state(with_pressure=False)
-                inputs.append((u, inputs[-1][0]))
-            for k in range(len(inputs) - 1, -1, -1):
-                fwd = torch.cat([inputs[k][0], inputs[k][1]], 0)
-                adj_in[0:3], adj_in[3:6], adj_in[6:9] = ub, upb, Nb
-                out = S.step_adjoint(fwd, adj_in)
-                ub, upb, Nb = out[0:3], out[3:6], out[6:9]
+                m = end - 1 - k
+                S.get_state(with_pressure=False, out=seg[3 * m:3 * m + 3])
+            for k in range(end - 1, start - 1, -1):
+                m = end - 1 - k
+                S.step_adjoint(seg[3 * m:3 * m + 6], bufs[cur], bufs[1 - cur])
+                cur = 1 - cur
         # initial history: u^{-1} = u^0 and N^{-1} = N(u^0)
-        adj_in[0:3], adj_in[3:6], adj_in[6:9] = ub, upb, Nb
-        g = S.adjoint_initial_history(ctx.u0, adj_in)
+        g = S.adjoint_initial_history(ctx.u0, bufs[cur])
         return g, None, None, None, None
 
 
