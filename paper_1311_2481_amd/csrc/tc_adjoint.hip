@@ -372,6 +372,12 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
     e = (x);      \
     if (e != hipSuccess) return hip_check(c, e, "adjoint step"); \
   } while (0)
+  if (c->flin) {
+    // grids the line kernels take: the whole chain below in one launch
+    TC_TRY(launch_pc_adj_line(c, ubn, nin, out_u, out_up, out_np, ntot));
+    TC_TRY(adjoint_nonlinear(c, u, ntot, ukeep, out_u, nl6, inter));
+    return TC_OK;
+  }
   // correction and velocity predictor, transposed
   hipLaunchKernelGGL(k_adj_phi, grd, blk, 0, st, c->rc_dev, d, ubn, phib);
   TC_TRY(hipGetLastError());

@@ -166,6 +166,11 @@ hipError_t launch_pc_line(tc_ctx* c, const cd* u, const cd* u_prev, const cd* N,
                           cd* p, int want_p, cd* omg);
 // transposed solves on the line layout (the arguments of launch_solve_t)
 hipError_t launch_solve_t_line(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x);
+// the adjoint step's predictor-corrector part on the line layout: from the
+// cotangents of u^{i+1} (ub) and N^i (nin) to those of u^i (out_u, before
+// the nonlinear term's part), u^{i-1}, N^{i-1} and the total cotangent of
+// N(u^i) (ntot); 3 fields each
+hipError_t launch_pc_adj_line(tc_ctx* c, const cd* ub, const cd* nin, cd* out_u, cd* out_up, cd* out_np, cd* ntot);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

@@ -581,6 +581,219 @@ __global__ __launch_bounds__(WAVES * NLANE) void k_solve_tl(const double* __rest
   (void)M;
 }
 
+// Adjoint of the predictor-corrector on the line layout: the chain of the
+// adjoint step (tc_adjoint.hip) from the cotangent u_bar' of u^{i+1} and
+// N_bar of N^i to the cotangents of u^i, u^{i-1}, N^{i-1} and the total
+// cotangent of N(u^i), with every intermediate on chip:
+//   phi_bar = -grad^H u_bar' (0 for mode (0,0))      r_phi = P^-T phi_bar
+//   u*_bar = u_bar' + div^H(I r_phi)                 r_u = H^-T u*_bar
+//   p_bar = grad^H(I r_u)                            r_p = P^-T p_bar
+//   Ne_bar = I r_u - div^H(I r_p) - (W r_p)/2
+//   u_bar = -(2/dt) I r_u + 2 V,  u_prev_bar = I r_u/(2dt) - V,
+//   V = (L+^T W r_p, L-^T W r_p)/2 (zero past HW rows from the walls)
+//   N_prev_bar = -Ne_bar,  N_tot = 2 Ne_bar + N_bar
+// (I: interior rows, W: the wall rows of the consistent Neumann condition,
+// not the outer row of mode (0,0)).  D1^T sums, for row k, the D1 weights
+// of rows k-4 .. k+4 in column k, in that order; the per-row table holds
+// those transposed weights.
+template <int LPS>
+__global__ __launch_bounds__(WAVES * NLANE) void k_pcl_adj(const double* __restrict__ rc,
+                                                          const double* __restrict__ flin, Dims d,
+                                                          const cd* __restrict__ ub, const cd* __restrict__ nin,
+                                                          cd* __restrict__ out_u, cd* __restrict__ out_up,
+                                                          cd* __restrict__ out_np, cd* __restrict__ ntot, int ntile,
+                                                          int per) {
+  constexpr int SPW = NLANE / LPS;
+  __shared__ double tab[RPL * TAB_F * LPS];
+  __shared__ cd vel[WAVES * 3 * RPL * NLANE];
+  const int lane = threadIdx.x % NLANE, wv = threadIdx.x / NLANE;
+  const int seg = lane / LPS, ch = lane % LPS;
+  const int M = d.n_r - 1;
+  // transposed D1 weights: entry m of row k multiplies row i = k + m - 4,
+  // and is D1[i][k] (zero for rows past the walls)
+  for (int i = threadIdx.x; i < RPL * TAB_F * LPS; i += blockDim.x) {
+    const int k = i % LPS, rf = i / LPS, r = rf / TAB_F, f = rf % TAB_F;
+    const int row = RPL * k + r;
+    double v;
+    if (f < NB9) {
+      const int src = row + f - HW;
+      v = (src >= 0 && src <= M) ? rc[(int64_t)src * RC_N + RC_W1 + (NB9 - 1 - f)] : 0.0;
+    } else {
+      v = rc[(int64_t)row * RC_N + RC_IR];
+    }
+    tab[i] = v;
+  }
+  __syncthreads();
+  const int x = blockIdx.x % 8, rr = blockIdx.x / 8;
+  const int t = x * per + rr / 8, q = rr % 8;
+  if (t >= ntile) return;
+  const int sign = q & 1;
+  const int dm = ((t * 4 + (q >> 1)) * WAVES + wv) * SPW + seg;
+  const bool active = dm < d.ndm;
+  if (__ballot(active) == 0) return;
+  const int dmc = active ? dm : d.ndm - 1;
+  const int labs = dmc / d.mt, n = dmc - labs * d.mt;
+  const bool nyq = active && sign == 1 && labs == 0;
+  const bool reg = active && !nyq;
+  const int64_t F = d.F, S = d.S;
+  const int j0 = RPL * ch;
+  if (nyq) {
+    const int64_t on = (int64_t)d.nyq * d.mt + n;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t oj = c * F + (int64_t)(j0 + r) * S + on;
+        out_u[oj] = z0();
+        out_up[oj] = z0();
+        out_np[oj] = z0();
+        ntot[oj] = z0();
+      }
+  }
+  const int s = sign ? d.mz - labs : labs;
+  const int64_t o = reg ? (int64_t)s * d.mt + n : 0;
+  const double a = n * d.kt, b = (sign ? -labs : labs) * d.kz;
+  const bool zero_mode = labs == 0 && n == 0;
+  const double* fl = flin + (int64_t)dmc * LINE_Q * 2 * LPS + 2 * ch;
+  const int64_t fop = (int64_t)d.ndm * LINE_Q * 2 * LPS;
+  auto IR = [&](int r) { return tab[(r * TAB_F + TAB_IR) * LPS + ch]; };
+  auto V = [&](int c, int r) -> cd& { return vel[((wv * 3 + c) * RPL + r) * NLANE + lane]; };
+  // interior rows of the line (wall rows: row 0 of lane 0, row 7 of the last lane)
+  auto interior = [&](int r) { return !((ch == 0 && r == 0) || (ch == LPS - 1 && r == RPL - 1)); };
+  cd w[RPL + 2 * HW], x1[RPL];
+  const double c_dt = 1.0 / d.dt;
+
+  // 1. phi_bar = -grad^H u_bar', grad^H v = D1^T (v+ + v-) - (a/r) v+ + (a/r) v- - i b v_z
+  {
+    cd sm[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int64_t oj = (int64_t)(j0 + r) * S + o;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) V(c, r) = ub[c * F + oj];
+      sm[r] = cadd(V(0, r), V(1, r));
+    }
+    halo<LPS>(sm, w, lane, ch);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      cd g = d1_at<LPS>(tab, ch, r, w);
+      g = cadd(g, scl(csub(V(1, r), V(0, r)), a * IR(r)));
+      g = csub(g, imul(V(2, r), b));
+      x1[r] = zero_mode ? z0() : cd{-g.x, -g.y};
+    }
+  }
+  // 2. r_phi = P^-T phi_bar
+  line_solve_t<LPS, true>(fl + OP_P * fop, x1, lane, ch);
+  if (ch == 0) x1[0] = scl(x1[0], d.s0);
+  if (ch == LPS - 1 && !zero_mode) x1[RPL - 1] = scl(x1[RPL - 1], d.sM);
+  // 3. u*_bar = u_bar' + div^H(I r_phi) (in vel; mode (0,0): the transpose
+  //    of u^{i+1}+- = u*+- - u*_r maps (v+, v-) to ((v+ - v-)/2, (v- - v+)/2))
+  {
+    cd mr[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) mr[r] = interior(r) ? x1[r] : z0();
+    halo<LPS>(mr, w, lane, ch);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const double ir = IR(r);
+      const cd f = mr[r];
+      const cd dt = scl(d1_at<LPS>(tab, ch, r, w), 0.5);
+      cd vp = V(0, r), vm = V(1, r);
+      if (zero_mode) {
+        vp = scl(csub(V(0, r), V(1, r)), 0.5);
+        vm = cd{-vp.x, -vp.y};
+      }
+      V(0, r) = cadd(vp, cadd(dt, scl(f, 0.5 * (1.0 + a) * ir)));
+      V(1, r) = cadd(vm, cadd(dt, scl(f, 0.5 * (1.0 - a) * ir)));
+      V(2, r) = csub(V(2, r), imul(f, b));
+    }
+  }
+  // 4. r_u = H^-T u*_bar
+#pragma unroll 1
+  for (int c = 0; c < 3; ++c) {
+    cd f[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) f[r] = V(c, r);
+    line_solve_t<LPS, false>(fl + (OP_HP + c) * fop, f, lane, ch);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) V(c, r) = interior(r) ? f[r] : z0();  // I r_u
+  }
+  // 5. p_bar = grad^H(I r_u), then r_p = P^-T p_bar
+  {
+    cd sm[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) sm[r] = cadd(V(0, r), V(1, r));
+    halo<LPS>(sm, w, lane, ch);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      cd g = d1_at<LPS>(tab, ch, r, w);
+      g = cadd(g, scl(csub(V(1, r), V(0, r)), a * IR(r)));
+      x1[r] = csub(g, imul(V(2, r), b));
+    }
+  }
+  line_solve_t<LPS, true>(fl + OP_P * fop, x1, lane, ch);
+  if (ch == 0) x1[0] = scl(x1[0], d.s0);
+  if (ch == LPS - 1 && !zero_mode) x1[RPL - 1] = scl(x1[RPL - 1], d.sM);
+  // 6. Ne_bar, the cotangents of u^i, u^{i-1}, N^{i-1} and N_tot
+  {
+    cd mr[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) mr[r] = interior(r) ? x1[r] : z0();
+    halo<LPS>(mr, w, lane, ch);
+    // wall terms: w_r at row 0 (lane 0) or row M (last lane; not for mode (0,0))
+    const bool wl = (ch == 0) || (ch == LPS - 1 && !zero_mode);
+    const int jw = ch == 0 ? 0 : M;
+    const cd ww = ch == 0 ? x1[0] : x1[RPL - 1];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = j0 + r;
+      const int64_t oj = (int64_t)j * S + o;
+      const double ir = IR(r);
+      const cd f = mr[r];
+      const cd dt = scl(d1_at<LPS>(tab, ch, r, w), 0.5);
+      cd ne[3] = {V(0, r), V(1, r), V(2, r)};  // I r_u
+      cd ou[3], oup[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ou[c] = scl(ne[c], -2.0 * c_dt);
+        oup[c] = scl(ne[c], 0.5 * c_dt);
+      }
+      ne[0] = csub(ne[0], cadd(dt, scl(f, 0.5 * (1.0 + a) * ir)));
+      ne[1] = csub(ne[1], cadd(dt, scl(f, 0.5 * (1.0 - a) * ir)));
+      ne[2] = cadd(ne[2], imul(f, b));
+      const int k = j - jw + HW;  // place of row j in the wall row's stencil
+      if (wl && k >= 0 && k < NB9) {
+        const cd wj = (j == jw) ? ww : z0();
+        ne[0] = csub(ne[0], scl(wj, 0.5));
+        ne[1] = csub(ne[1], scl(wj, 0.5));
+        // L+-^T w = D2^T w + D1^T(w / r) - (a^2/r^2 + b^2 + (1 +- 2a)/r^2) w
+        const double* Rw = rc + (int64_t)jw * RC_N;
+        // column j of the wall row's stencils: weight k = j - jw + HW
+        const cd t2 = scl(ww, Rw[RC_W2 + k]);
+        const cd t1 = scl(scl(ww, Rw[RC_IR]), Rw[RC_W1 + k]);
+        const cd base = cadd(t2, t1);
+        const double ir2 = rc[(int64_t)j * RC_N + RC_IR2];
+        const double dd = a * a * ir2 + b * b;
+        const cd vp = scl(csub(base, scl(wj, dd + (1.0 + 2.0 * a) * ir2)), 0.5);
+        const cd vm = scl(csub(base, scl(wj, dd + (1.0 - 2.0 * a) * ir2)), 0.5);
+        ou[0] = cadd(ou[0], scl(vp, 2.0));
+        ou[1] = cadd(ou[1], scl(vm, 2.0));
+        oup[0] = csub(oup[0], vp);
+        oup[1] = csub(oup[1], vm);
+      }
+      if (reg) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          out_u[c * F + oj] = ou[c];
+          out_up[c * F + oj] = oup[c];
+          out_np[c * F + oj] = cd{-ne[c].x, -ne[c].y};
+          ntot[c * F + oj] = cadd(scl(ne[c], 2.0), nin[c * F + oj]);
+        }
+      }
+    }
+  }
+}
+
 // Lanes per slot where the line kernel runs: n_r = 8 LPS with LPS = 4, 8
 // or 16.  Longer lines need 32 or 64 lanes per slot, whose loads touch as
 // many cache lines per instruction; there the four-sweep kernels, which
@@ -624,6 +837,27 @@ hipError_t launch_solve_t_line(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x
     case 4: return launch_solve_t_lps<4>(c, op0, nop, rhs, x);
     case 8: return launch_solve_t_lps<8>(c, op0, nop, rhs, x);
     case 16: return launch_solve_t_lps<16>(c, op0, nop, rhs, x);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LPS>
+static hipError_t launch_pc_adj_lps(tc_ctx* c, const cd* ub, const cd* nin, cd* out_u, cd* out_up, cd* out_np,
+                                    cd* ntot) {
+  const Dims& d = c->d;
+  constexpr int SPW = NLANE / LPS;
+  const int ntile = (d.ndm + 16 * SPW - 1) / (16 * SPW);
+  const int per = (ntile + 7) / 8;
+  hipLaunchKernelGGL((k_pcl_adj<LPS>), dim3(64 * per), dim3(WAVES * NLANE), 0, c->stream, c->rc_dev, c->flin, d, ub,
+                     nin, out_u, out_up, out_np, ntot, ntile, per);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_adj_line(tc_ctx* c, const cd* ub, const cd* nin, cd* out_u, cd* out_up, cd* out_np, cd* ntot) {
+  switch (line_lps(c->d)) {
+    case 4: return launch_pc_adj_lps<4>(c, ub, nin, out_u, out_up, out_np, ntot);
+    case 8: return launch_pc_adj_lps<8>(c, ub, nin, out_u, out_up, out_np, ntot);
+    case 16: return launch_pc_adj_lps<16>(c, ub, nin, out_u, out_up, out_np, ntot);
     default: return hipErrorInvalidValue;
   }
 }

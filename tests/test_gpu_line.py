@@ -109,3 +109,30 @@ def test_line_transposed_solve_matches_oracle(case, kind, monkeypatch):
     # the empty axial slot is written as zero (the output array is not cleared first)
     assert np.all(x[:, cfg.m_z // 2] == 0)
     S.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_line_adjoint_step_matches_oracle(case, monkeypatch):
+    """The adjoint step with its predictor-corrector part on the line layout
+    (one fused launch) against the oracle's adjoint step, and against the
+    same step through the separate stencil and solve kernels."""
+    from oracle import adjoint as adj
+    S, P, cfg = _pair(case, monkeypatch, dt=1e-5)
+    R, _, _ = _pair(case, monkeypatch, line=False, dt=1e-5)
+    u = tc_inputs.initial_state(P.r, cfg)
+    shape = (3, cfg.n_r, cfg.m_z, cfg.m_theta)
+    a, b, c = (tc_inputs.random_state(shape, 60 + k, hermitian=False) for k in range(3))
+    fwd, adj_in = to_dev(np.concatenate([u, u])), to_dev(np.concatenate([a, b, c]))
+    out = to_host(S.step_adjoint(fwd, adj_in))
+    alt = to_host(R.step_adjoint(fwd, adj_in))
+    ref = adj.step_adjoint(P, u, a, b, c)
+    errs = [rel_l2(out[3 * k:3 * k + 3], ref[k]) for k in range(3)]
+    alts = [rel_l2(out[3 * k:3 * k + 3], alt[3 * k:3 * k + 3]) for k in range(3)]
+    floors = [twin_floor(P, lambda Q: adj.step_adjoint(Q, u, a, b, c)[k], ref[k]) for k in range(3)]
+    print(f"line adjoint step {case}: rel_l2 vs oracle u {errs[0]:.2e}, u_prev {errs[1]:.2e}, N_prev {errs[2]:.2e} "
+          f"(floors {floors[0]:.2e} {floors[1]:.2e} {floors[2]:.2e}); vs separate kernels "
+          f"{alts[0]:.2e} {alts[1]:.2e} {alts[2]:.2e}")
+    for e, f, x in zip(errs, floors, alts):
+        assert e <= floor_tol(f) and x <= floor_tol(f)
+    S.close()
+    R.close()
