@@ -99,8 +99,9 @@ __device__ __forceinline__ void operator_row(const double* rc, const Dims& d, in
 }
 
 // Running factorization of one operator in its processing order (ascending
-// rows for P, descending for the Helmholtz operators): U[q] is the U-row
-// (pivot and the 4 entries after it) of the row q+1 places earlier.
+// rows for P, descending for the Helmholtz operators): U[q] is the U-row of
+// the row q+1 places earlier, its inverse pivot in U[q][0] and the 4
+// entries after the pivot in U[q][1..4].
 struct Elim {
   double U[4][5];
   __device__ __forceinline__ void reset() {
@@ -112,16 +113,18 @@ struct Elim {
   // Next row: ip = its place in processing order, row its entries in
   // processing column order (entry HW on the diagonal).  Gives the
   // multipliers of the 4 previous rows (mult[q-1]: the row q places
-  // earlier) and leaves the row's U-row in row[HW .. HW+4] and in U[0].
+  // earlier, the eliminated entry times that row's inverse pivot), leaves
+  // the row's pivot and the entries after it in row[HW .. HW+4] and its
+  // inverse pivot and those entries in U[0].
   __device__ __forceinline__ void next(double (&row)[NB9], int ip, double (&mult)[4]) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int q = 4; q >= 1; --q) {
       double m = 0.0;
       if (ip - q >= 0) {
-        m = row[HW - q] / U[q - 1][0];
+        m = row[HW - q] * U[q - 1][0];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) row[HW - q + c] -= m * U[q - 1][c];
+        for (int c = 1; c < 5; ++c) row[HW - q + c] -= m * U[q - 1][c];
       }
       mult[q - 1] = m;
     }
@@ -129,8 +132,9 @@ struct Elim {
     for (int q = 3; q >= 1; --q)
 #pragma unroll
       for (int c = 0; c < 5; ++c) U[q][c] = U[q - 1][c];
+    U[0][0] = 1.0 / row[HW];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) U[0][c] = row[HW + c];
+    for (int c = 1; c < 5; ++c) U[0][c] = row[HW + c];
   }
   // multipliers of row j of operator op (processing place ip)
   __device__ __forceinline__ void row_mult(const double* rc, const Dims& d, int op, int j, int ip, double a, double b,
@@ -166,7 +170,7 @@ __global__ void k_factor(const double* __restrict__ rc, double* __restrict__ fac
     const double piv = row[HW];
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) flag = 1;
     double sec[5];  // inverse pivot, second-sweep coefficients
-    sec[0] = 1.0 / piv;
+    sec[0] = E.U[0][0];
     for (int c = 1; c <= 4; ++c) sec[c] = (ip + c <= M) ? row[HW + c] : 0.0;
     for (int c = 0; c <= 4; ++c) F[(int64_t)(4 + c) * d.ndm] = sec[c];
     if (flin) {
