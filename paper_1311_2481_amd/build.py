@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["tc_api.hip", "tc_solve.hip", "tc_line.hip", "tc_nonlinear.hip", "tc_adjoint.hip", "tc_optimal.hip"]
+SOURCES = ["tc_api.hip", "tc_solve.hip", "tc_line.hip", "tc_nonlinear.hip", "tc_adjoint.hip", "tc_adjoint_pc.hip", "tc_optimal.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed fp32 ops are kept off in all device code

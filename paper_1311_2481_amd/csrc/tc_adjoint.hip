@@ -18,12 +18,14 @@
 // and the nonlinear term's adjoint (transposed transforms, see the azimuthal
 // adjoint kernel) applied to N_bar_total = 2 Ne_bar + N_bar.
 //
-// Work decomposition: one thread per (radial node, stored mode) point, in
-// tiles of consecutive slots of one node, numbered node-fastest and walked
-// per XCD (see make_slot); D1^T is applied by gathering the (up to 9) rows
-// whose stencils touch a node, from fields written by an earlier launch,
-// with masks and sums of fields applied on the fly.  The banded
-// transposed solves run the three Helmholtz operators in one launch.
+// The predictor-corrector part runs fused: in four sweeps over the radial
+// rows (tc_adjoint_pc.hip), or with each mode's radial line on chip on the
+// grids the line kernels take (tc_line.hip).  The nonlinear term's adjoint
+// follows: the transposed transforms, then the curl's adjoint below, one
+// thread per (radial node, stored mode) point, in tiles of consecutive
+// slots of one node, numbered node-fastest and walked per XCD (see
+// make_slot); D1^T is applied by gathering the (up to 9) rows whose
+// stencils touch a node.
 #include "tc_internal.h"
 
 namespace tc {
@@ -98,136 +100,6 @@ __device__ __forceinline__ cd gather_t(const double* rc, const Dims& d, int k, i
 
 }  // namespace
 
-// phi_bar = -grad^H(u_bar'), grad^H v = D1^T (v+ + v-) - (a/r) v+ + (a/r) v- - i b v_z.
-__global__ void k_adj_phi(const double* __restrict__ rc, Dims d, const cd* __restrict__ ub, cd* __restrict__ out) {
-  Slot q;
-  if (!make_slot(d, q)) return;
-  const int k = q.k;
-  const int64_t o = k * d.S + q.idx;
-  // mode (0,0) takes no gradient of phi (its correction is -u*_r instead)
-  if (q.nyq || q.zero_mode) {
-    out[o] = cz();
-    return;
-  }
-  const double ir = rc[(int64_t)k * RC_N + RC_IR];
-  cd g = gather_t(rc, d, k, RC_W1, [&](int i) { return cpl(ub[i * d.S + q.idx], ub[d.F + i * d.S + q.idx]); });
-  g = cpl(g, cs(cmi(ub[d.F + o], ub[o]), q.a * ir));
-  g = cmi(g, cimul(ub[2 * d.F + o], q.b));
-  out[o] = cd{-g.x, -g.y};
-}
-
-// u*_bar = u_bar' + div^H(I r), div^H f = (D1^T f/2 + (1+a) f/(2r), D1^T f/2 + (1-a) f/(2r), -i b f),
-// I: interior rows.
-__global__ void k_adj_ustar(const double* __restrict__ rc, Dims d, const cd* __restrict__ ub, const cd* __restrict__ r,
-                            cd* __restrict__ us) {
-  Slot q;
-  if (!make_slot(d, q)) return;
-  const int M = d.n_r - 1;
-  const int k = q.k;
-  const int64_t o = k * d.S + q.idx;
-  if (q.nyq) {
-    us[o] = us[d.F + o] = us[2 * d.F + o] = cz();
-    return;
-  }
-  auto mr = [&](int i) { return (i == 0 || i == M) ? cz() : r[i * d.S + q.idx]; };
-  const double ir = rc[(int64_t)k * RC_N + RC_IR];
-  const cd f = mr(k);
-  const cd dt = cs(gather_t(rc, d, k, RC_W1, mr), 0.5);
-  // mode (0,0): u^{i+1}+- = u*+- - u*_r, whose transpose maps (v+, v-) to
-  // ((v+ - v-)/2, (v- - v+)/2)
-  cd vp = ub[o], vm = ub[d.F + o];
-  if (q.zero_mode) {
-    vp = cs(cmi(ub[o], ub[d.F + o]), 0.5);
-    vm = cd{-vp.x, -vp.y};
-  }
-  us[o] = cpl(vp, cpl(dt, cs(f, 0.5 * (1.0 + q.a) * ir)));
-  us[d.F + o] = cpl(vm, cpl(dt, cs(f, 0.5 * (1.0 - q.a) * ir)));
-  us[2 * d.F + o] = cmi(ub[2 * d.F + o], cimul(f, q.b));
-}
-
-// From rhs_u_bar (interior rows r of ru): u_bar = -(2/dt) r, u_prev_bar = r/(2dt),
-// p_bar = grad^H r.  (Ne_bar = r is read from ru by the pressure-RHS kernel.)
-__global__ void k_adj_rhsu(const double* __restrict__ rc, Dims d, const cd* __restrict__ ru, cd* __restrict__ u_b,
-                           cd* __restrict__ up_b, cd* __restrict__ p_b) {
-  Slot q;
-  if (!make_slot(d, q)) return;
-  const int M = d.n_r - 1;
-  const int k = q.k;
-  const int64_t o = k * d.S + q.idx;
-  auto mr = [&](int c, int i) { return (i == 0 || i == M || q.nyq) ? cz() : ru[c * d.F + i * d.S + q.idx]; };
-  for (int c = 0; c < 3; ++c) {
-    const cd r = mr(c, k);
-    u_b[c * d.F + o] = cs(r, -2.0 / d.dt);
-    up_b[c * d.F + o] = cs(r, 0.5 / d.dt);
-  }
-  if (q.nyq) {
-    p_b[o] = cz();
-    return;
-  }
-  const double ir = rc[(int64_t)k * RC_N + RC_IR];
-  cd g = gather_t(rc, d, k, RC_W1, [&](int i) { return cpl(mr(0, i), mr(1, i)); });
-  g = cpl(g, cs(cmi(mr(1, k), mr(0, k)), q.a * ir));
-  g = cmi(g, cimul(mr(2, k), q.b));
-  p_b[o] = g;
-}
-
-// Pressure-RHS adjoint: Ne_bar = I ru (the interior rows of rhs_u_bar)
-// minus div^H(I rp) and -(W rp)/2 on Ne+-, with W the wall rows of the
-// consistent Neumann condition (not the outer row of mode (0,0));
-// V_r^H(W rp) = ((L+^T w)/2, (L-^T w)/2): u_bar += 2 V, u_prev_bar -= V.
-// V vanishes more than HW rows from both walls, where u_bar and u_prev_bar
-// are left untouched.  Also writes N_prev_bar = -Ne_bar and
-// N_tot = 2 Ne_bar + N_bar_in.
-__global__ void k_adj_rhsp(const double* __restrict__ rc, Dims d, const cd* __restrict__ rp, const cd* __restrict__ ru,
-                           cd* __restrict__ u_b, cd* __restrict__ up_b, const cd* __restrict__ n_in,
-                           cd* __restrict__ n_prev_b, cd* __restrict__ n_tot) {
-  Slot q;
-  if (!make_slot(d, q)) return;
-  const int M = d.n_r - 1;
-  const int k = q.k;
-  const int64_t o = k * d.S + q.idx;
-  if (q.nyq) {
-    for (int c = 0; c < 3; ++c)
-      u_b[c * d.F + o] = up_b[c * d.F + o] = n_prev_b[c * d.F + o] = n_tot[c * d.F + o] = cz();
-    return;
-  }
-  auto mr = [&](int i) { return (i == 0 || i == M) ? cz() : rp[i * d.S + q.idx]; };
-  auto wr = [&](int i) {
-    const bool wall = (i == 0 || i == M) && !(i == M && q.zero_mode);
-    return wall ? rp[i * d.S + q.idx] : cz();
-  };
-  const double ir = rc[(int64_t)k * RC_N + RC_IR];
-  const double ir2 = rc[(int64_t)k * RC_N + RC_IR2];
-  cd ne[3] = {cz(), cz(), cz()};
-  if (k != 0 && k != M)
-    for (int c = 0; c < 3; ++c) ne[c] = ru[c * d.F + o];
-  const cd f = mr(k);
-  const cd dt = cs(gather_t(rc, d, k, RC_W1, mr), 0.5);
-  ne[0] = cmi(ne[0], cpl(dt, cs(f, 0.5 * (1.0 + q.a) * ir)));
-  ne[1] = cmi(ne[1], cpl(dt, cs(f, 0.5 * (1.0 - q.a) * ir)));
-  ne[2] = cpl(ne[2], cimul(f, q.b));  // -(-i b f)
-  if (k <= HW || k >= M - HW) {
-    const cd w = wr(k);
-    ne[0] = cmi(ne[0], cs(w, 0.5));
-    ne[1] = cmi(ne[1], cs(w, 0.5));
-    // L+-^T w = D2^T w + D1^T(w / r) - (a^2/r^2 + b^2 + (1 +- 2a)/r^2) w
-    const cd t2 = gather_t(rc, d, k, RC_W2, wr);
-    const cd t1 = gather_t(rc, d, k, RC_W1, [&](int i) { return cs(wr(i), rc[(int64_t)i * RC_N + RC_IR]); });
-    const cd base = cpl(t2, t1);
-    const double dd = q.a * q.a * ir2 + q.b * q.b;
-    const cd vp = cs(cmi(base, cs(w, dd + (1.0 + 2.0 * q.a) * ir2)), 0.5);
-    const cd vm = cs(cmi(base, cs(w, dd + (1.0 - 2.0 * q.a) * ir2)), 0.5);
-    u_b[o] = cpl(u_b[o], cs(vp, 2.0));
-    u_b[d.F + o] = cpl(u_b[d.F + o], cs(vm, 2.0));
-    up_b[o] = cmi(up_b[o], vp);
-    up_b[d.F + o] = cmi(up_b[d.F + o], vm);
-  }
-  for (int c = 0; c < 3; ++c) {
-    n_prev_b[c * d.F + o] = cd{-ne[c].x, -ne[c].y};
-    n_tot[c * d.F + o] = cpl(cs(ne[c], 2.0), n_in[c * d.F + o]);
-  }
-}
-
 // Curl adjoint: from the direct cotangents (u+d, u-d, u_zd) and those of
 // omega (o+, o-, o_z) to the cotangent of (u+, u-, u_z); adds it and
 // u_bar_keep into out (which holds the predictor-corrector part).
@@ -270,13 +142,16 @@ using namespace tc;
 
 namespace {
 
-// Work space of the adjoint calls: 13 fields + the 9-field transform
-// buffer (double), allocated on first use.
+// Work space of the adjoint calls (allocated on first use): AUX_FIELDS
+// fields, then the 9-field transform buffer (double).  Fields: 0, the U^T
+// sweeps' output (1 field); 1-6, the nonlinear cotangents (6 fields; fields
+// 1-3 first hold the Helmholtz U^T outputs); 7-9, N_tot (3 fields).
+constexpr int AUX_FIELDS = 10, AUX_NL6 = 1, AUX_NTOT = 7;
 tc_status ensure_aux(tc_ctx* c) {
   const Dims& d = c->d;
   const size_t FB = (size_t)d.F * sizeof(cd);
   const size_t inter9 = (size_t)9 * d.pz * d.mt * sizeof(cd) * d.n_r;
-  const size_t need = 13 * FB + inter9;
+  const size_t need = AUX_FIELDS * FB + inter9;
   if (c->aux_bytes >= need) return TC_OK;
   if (c->aux) {
     (void)hipFree(c->aux);
@@ -342,18 +217,13 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
     const char* b = static_cast<const char*>(adj_out);
     if (a < b + 9 * FB && b < a + 9 * FB) return fail(c, TC_EINVAL, "adj_in and adj_out overlap");
   }
-  const int NW = 13;
   if (tc_status sa = ensure_aux(c); sa != TC_OK) return sa;
   cd* w = c->aux;
-  cd* phib = w + 0 * F;
-  cd* rphi = w + 1 * F;
-  cd* us = w + 2 * F;    // 3
-  cd* ru = w + 5 * F;    // 3
-  cd* pb = w + 8 * F;
-  cd* rp = w + 9 * F;
-  cd* ntot = w + 10 * F;  // 3 (10..12), then the 6 nonlinear cotangents reuse us/ru
-  cd* nl6 = us;           // 6 fields: us (3) + ru (3), free by then
-  void* inter = w + NW * F;
+  cd* wA = w;                   // 1 field
+  cd* nl6 = w + AUX_NL6 * F;    // 6 fields
+  cd* wH = nl6;                 // 3 fields, free again before nl6 is written
+  cd* ntot = w + AUX_NTOT * F;  // 3 fields
+  void* inter = w + AUX_FIELDS * F;
 
   const cd* u = static_cast<const cd*>(fwd);
   const cd* ubn = static_cast<const cd*>(adj_in);
@@ -364,34 +234,16 @@ extern "C" tc_status tc_step_adjoint(tc_ctx* c, const void* fwd, const void* adj
   cd* out_up = out + 3 * F;
   cd* out_np = out + 6 * F;
 
-  const dim3 blk(SLOT_BLOCK), grd((unsigned)(8 * ((slot_tiles(d) + 7) / 8)));
-  hipStream_t st = c->stream;
   hipError_t e;
 #define TC_TRY(x) \
   do {            \
     e = (x);      \
     if (e != hipSuccess) return hip_check(c, e, "adjoint step"); \
   } while (0)
-  if (c->flin) {
-    // grids the line kernels take: the whole chain below in one launch
-    TC_TRY(launch_pc_adj_line(c, ubn, nin, out_u, out_up, out_np, ntot));
-    TC_TRY(adjoint_nonlinear(c, u, ntot, ukeep, out_u, nl6, inter));
-    return TC_OK;
-  }
-  // correction and velocity predictor, transposed
-  hipLaunchKernelGGL(k_adj_phi, grd, blk, 0, st, c->rc_dev, d, ubn, phib);
-  TC_TRY(hipGetLastError());
-  TC_TRY(launch_solve_t(c, OP_P, 1, phib, rphi));
-  hipLaunchKernelGGL(k_adj_ustar, grd, blk, 0, st, c->rc_dev, d, ubn, rphi, us);
-  TC_TRY(hipGetLastError());
-  TC_TRY(launch_solve_t(c, OP_HP, 3, us, ru));
-  hipLaunchKernelGGL(k_adj_rhsu, grd, blk, 0, st, c->rc_dev, d, ru, out_u, out_up, pb);
-  TC_TRY(hipGetLastError());
-  // pressure predictor, transposed
-  TC_TRY(launch_solve_t(c, OP_P, 1, pb, rp));
-  hipLaunchKernelGGL(k_adj_rhsp, grd, blk, 0, st, c->rc_dev, d, rp, ru, out_u, out_up, nin, out_np, ntot);
-  TC_TRY(hipGetLastError());
-  // nonlinear term, transposed: forward fields u, omega(u) and the cotangent N_tot
+  // predictor-corrector, transposed, then the nonlinear term, transposed:
+  // forward fields u, omega(u) and the cotangent N_tot
+  if (c->flin) TC_TRY(launch_pc_adj_line(c, ubn, nin, out_u, out_up, out_np, ntot));
+  else TC_TRY(launch_pc_adj(c, ubn, nin, out_u, out_up, out_np, ntot, wA, wH));
   TC_TRY(adjoint_nonlinear(c, u, ntot, ukeep, out_u, nl6, inter));
 #undef TC_TRY
   return TC_OK;
@@ -415,6 +267,7 @@ extern "C" tc_status tc_adjoint_initial_history(tc_ctx* c, const void* u0, const
   cd* out = static_cast<cd*>(g);
   hipError_t e = hipMemcpyAsync(out, ub, 3 * FB, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
-    e = adjoint_nonlinear(c, static_cast<const cd*>(u0), ub + 6 * F, ub + 3 * F, out, c->aux + 2 * F, c->aux + 13 * F);
+    e = adjoint_nonlinear(c, static_cast<const cd*>(u0), ub + 6 * F, ub + 3 * F, out, c->aux + AUX_NL6 * F,
+                          c->aux + AUX_FIELDS * F);
   return hip_check(c, e, "tc_adjoint_initial_history");
 }

@@ -171,6 +171,10 @@ hipError_t launch_solve_t_line(tc_ctx* c, int op0, int nop, const cd* rhs, cd* x
 // the nonlinear term's part), u^{i-1}, N^{i-1} and the total cotangent of
 // N(u^i) (ntot); 3 fields each
 hipError_t launch_pc_adj_line(tc_ctx* c, const cd* ub, const cd* nin, cd* out_u, cd* out_up, cd* out_np, cd* ntot);
+// the same in four sweeps (tc_adjoint_pc.hip), for the other grids; wA (1
+// field) and wH (3 fields) are work space
+hipError_t launch_pc_adj(tc_ctx* c, const cd* ub, const cd* nin, cd* out_u, cd* out_up, cd* out_np, cd* ntot, cd* wA,
+                         cd* wH);
 hipError_t launch_curl(tc_ctx* c, const cd* u, cd* omega);
 hipError_t launch_zinv(tc_ctx* c, int plane0, int nplanes, const cd* u, const cd* omega);
 hipError_t launch_theta(tc_ctx* c, int nplanes);

@@ -201,3 +201,31 @@ def test_differentiation_workload_gradient_vs_oracle_reference():
           f"projections rel max {ep:.2e}, sampled coefficients max / |g| {es:.2e}")
     assert eJ < 1e-10 and en < 1e-9 and ep < 1e-9 and es < 1e-10
     S.close()
+
+
+@pytest.mark.parametrize("n_r,line_off", [(40, False), (64, True)])
+def test_adjoint_four_sweeps_match_oracle(n_r, line_off, monkeypatch):
+    """The adjoint step's predictor-corrector part in four fused sweeps (the
+    grids the line kernels do not take: here 40 radial nodes, and 64 with the
+    line kernels switched off) against the oracle's adjoint step, on a
+    ragged mode count (m_theta = 12, m_z = 20)."""
+    if line_off:
+        monkeypatch.setenv("TC_PC_LINE", "0")
+    try:
+        S, P, cfg = make_pair("medium", n_r=n_r, m_theta=12, m_z=20, dt=1e-5)
+    finally:
+        monkeypatch.delenv("TC_PC_LINE", raising=False)
+    u = tc_inputs.initial_state(P.r, cfg)
+    shape = (3, cfg.n_r, cfg.m_z, cfg.m_theta)
+    a, b, c = (tc_inputs.random_state(shape, 70 + k, hermitian=False) for k in range(3))
+    out = to_host(S.step_adjoint(to_dev(np.concatenate([u, u])), to_dev(np.concatenate([a, b, c]))))
+    ref = adj.step_adjoint(P, u, a, b, c)
+    errs = [rel_l2(out[3 * k:3 * k + 3], ref[k]) for k in range(3)]
+    floors = [twin_floor(P, lambda Q: adj.step_adjoint(Q, u, a, b, c)[k], ref[k]) for k in range(3)]
+    print(f"four-sweep adjoint step n_r={n_r}: rel_l2 u {errs[0]:.2e}, u_prev {errs[1]:.2e}, N_prev {errs[2]:.2e}; "
+          f"floors {floors[0]:.2e} {floors[1]:.2e} {floors[2]:.2e}")
+    for e, f in zip(errs, floors):
+        assert e <= floor_tol(f)
+    # the empty axial slot is zero in every output
+    assert np.abs(out[:, :, cfg.m_z // 2]).max() == 0.0
+    S.close()
