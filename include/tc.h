@@ -110,7 +110,12 @@ typedef struct tc_ctx tc_ctx;
  * are computed once, each step only substitutes).  hip_stream: a
  * hipStream_t (NULL = default stream).  Waits for the factorisation to
  * finish.  Returns TC_EINVAL for an unsupported grid, TC_ESINGULAR if a
- * pivot is zero or not finite, TC_ENOMEM, TC_EHIP.  *out is NULL on error. */
+ * pivot is zero or not finite, TC_ENOMEM, TC_EHIP.  *out is NULL on error.
+ * On grids of 32, 64 or 128 radial nodes the context also keeps a second,
+ * lane-contiguous copy of the factors for the predictor-corrector kernels
+ * that hold each mode's radial line on chip; with the environment variable
+ * TC_PC_LINE=0 set at this call it uses the four-sweep kernels instead (the
+ * same results up to rounding) and keeps no copy. */
 tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double dt,
                   void* hip_stream, tc_ctx** out);
 
