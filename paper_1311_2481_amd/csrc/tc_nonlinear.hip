@@ -300,7 +300,11 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
     }
   };
   // per-plane magnitude of two of the input fields (see ZIo::zmax): a wave
-  // maximum, then one atomic per wave
+  // maximum, then the workgroup's over its waves, then one atomic per
+  // workgroup (all the workgroups of a plane update the same word, so
+  // fewer atomics contend less); the early returns are uniform over the
+  // workgroup, as its barrier needs
+  __shared__ float wave_max[(NF * TPF + 63) / 64];
   auto record = [&](int id, const cd (&raw)[FI::PER0][FI::R0]) {
     if (io.zmax == nullptr) return;
     const int rest = id / tiles;
@@ -313,8 +317,13 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
 #pragma unroll
       for (int q = 0; q < FI::R0; ++q) m = fmaxf(m, (float)fmax(fabs(raw[k][q].x), fabs(raw[k][q].y)));
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    // non-negative floats order as their bit patterns
-    if ((threadIdx.x & 63) == 0) atomicMax(io.zmax + ZMAX_WORDS * pl + which, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = fmaxf(m, wave_max[w]);
+      // non-negative floats order as their bit patterns
+      atomicMax(io.zmax + ZMAX_WORDS * pl + which, __float_as_uint(m));
+    }
   };
   const int id = single_tile(ntiles);
   if (id < 0) return;  // padding workgroup (uniform over the workgroup)
