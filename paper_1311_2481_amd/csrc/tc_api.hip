@@ -720,6 +720,7 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
   if (e == hipSuccess) e = hipMemsetAsync(c->N_prev, 0, 3 * FB, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->N_cur, 0, 3 * FB, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, FB, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->zmax, 0, (size_t)ZMAX_WORDS * d.n_r * sizeof(unsigned int), c->stream);
   int* bad = nullptr;
   if (e == hipSuccess) e = hipMalloc(&bad, sizeof(int));
   if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), c->stream);

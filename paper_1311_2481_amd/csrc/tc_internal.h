@@ -68,7 +68,9 @@ struct KernelTimer {
 // output is multiplied by scale (and by Hermitian weights when weights = 1).
 // zmax (inverse kernel, optional): per batch plane, ZMAX_WORDS words; input
 // field k adds its largest |component| (as float bits, a maximum) to word
-// zmax_slot[k] of its plane (-1: not recorded).  Cleared by the launcher.
+// zmax_slot[k] of its plane (-1: not recorded).  The words start at zero:
+// tc_init clears them, and the forward kernel, given zmax, clears the
+// batch's words for the next inverse pass.
 constexpr int ZMAX_WORDS = 4;
 struct ZIo {
   const C2<double>* src[9];

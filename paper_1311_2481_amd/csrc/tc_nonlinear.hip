@@ -154,10 +154,6 @@ __global__ __launch_bounds__(256) void k_curl_points(const double* __restrict__ 
   w[2 * F + o] = cd{0.5 * q.y, -0.5 * q.x};
 }
 
-__global__ void k_clear_words(unsigned int* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
-}
-
 template <int KIND>
 static hipError_t run_curl(tc_ctx* c, const cd* u, cd* out) {
   const int64_t blocks = (c->d.S + 255) / 256;
@@ -831,6 +827,10 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   const int ntiles = tiles * io.nfields * nplanes;
   const int f = threadIdx.x % NF, t = threadIdx.x / NF;
   const int h = d.half;
+  // per-plane magnitude words of the batch (see ZIo::zmax), read by the
+  // azimuthal pass that ran before this one: zero again for the next batch
+  if (io.zmax != nullptr && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < ZMAX_WORDS * nplanes; i += blockDim.x) io.zmax[i] = 0u;
   auto load = [&](int id, typename FF::In& v) {
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
@@ -968,9 +968,8 @@ hipError_t launch_zinv(tc_ctx* c, int plane0, int np, const cd* u, const cd* om)
     io.zmax = c->zmax;
     const int slot[6] = {2, 2, 0, 3, 3, 1};
     for (int k = 0; k < 9; ++k) io.zmax_slot[k] = k < 6 ? slot[k] : -1;
-    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, c->stream, c->zmax, ZMAX_WORDS * np);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // (the words start at zero: cleared at tc_init and by the forward axial
+    // pass that follows each azimuthal float pass)
   }
   return launch_zinv_io(c, plane0, np, io, c->inter, f32);
 }
@@ -1072,7 +1071,11 @@ hipError_t launch_zfwd(tc_ctx* c, int plane0, int np, cd* N) {
   io.nf_plane = inter_fields(c);
   io.scale = 1.0 / ((double)c->d.pt * (double)c->d.pz);
   io.weights = 0;
-  return launch_zfwd_io(c, plane0, np, io, c->inter, c->g.precision == TC_FP32_BULK);
+  const bool f32 = c->g.precision == TC_FP32_BULK;
+  // the per-plane magnitudes the azimuthal float pass has just used are
+  // cleared by this pass for the next axial inverse pass
+  if (f32 && TC_F32_ZSCALE) io.zmax = c->zmax;
+  return launch_zfwd_io(c, plane0, np, io, c->inter, f32);
 }
 
 hipError_t launch_zfwd_io(tc_ctx* c, int plane0, int np, const ZIo& io, const void* inter, bool f32) {
