@@ -31,20 +31,33 @@ tc_status hip_check(tc_ctx* c, hipError_t e, const char* what) {
 void timer_begin(tc_ctx* c, int which) {
   if (!c->timing) return;
   KernelTimer& t = c->timers[which];
+  t.open = false;
   if ((size_t)(t.used + 2) > t.ev.size()) {
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      (void)hipGetLastError();
+      return;  // this launch goes untimed
+    }
     t.ev.push_back(a);
     t.ev.push_back(b);
   }
-  hipEventRecord(t.ev[t.used], c->stream);
+  if (hipEventRecord(t.ev[t.used], c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  t.open = true;
 }
 
 void timer_end(tc_ctx* c, int which) {
   if (!c->timing) return;
   KernelTimer& t = c->timers[which];
-  if ((size_t)(t.used + 2) > t.ev.size()) return;
-  hipEventRecord(t.ev[t.used + 1], c->stream);
+  if (!t.open) return;
+  t.open = false;
+  if (hipEventRecord(t.ev[t.used + 1], c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
   t.used += 2;
 }
 

@@ -58,6 +58,7 @@ enum { TK_PC = 0, TK_CURL = 1, TK_ZINV = 2, TK_THETA = 3, TK_ZFWD = 4, TK_N = 5 
 struct KernelTimer {
   std::vector<hipEvent_t> ev;  // pairs
   int used = 0;
+  bool open = false;  // a start event is recorded and its end is not
   double ms = 0.0;
   int launches = 0;
 };

@@ -143,3 +143,26 @@ def test_line_adjoint_step_matches_oracle(case, monkeypatch):
         assert e <= floor_tol(f) and x <= floor_tol(f)
     S.close()
     R.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_line_multistep_call_equals_single_steps(case, monkeypatch):
+    """tc_step(5) (the pressure written on the last step only) gives the same
+    bits as five tc_step(1) calls from the same state: state, pressure,
+    history and the fused curl the next step uses."""
+    S, P, cfg = _pair(case, monkeypatch, dt=1e-5)
+    R, _, _ = _pair(case, monkeypatch, dt=1e-5)
+    u0, up, Np = _inputs(P, cfg, 85)
+    for X in (S, R):
+        X.set_state(to_dev(u0), to_dev(up), to_dev(Np))
+    S.step(5)
+    for _ in range(5):
+        R.step(1)
+    for a, b in zip(S.get_state() + S.get_history(), R.get_state() + R.get_history()):
+        assert np.array_equal(to_host(a), to_host(b))
+    # one more step each: the curl each kept for it is the same
+    S.step(1)
+    R.step(1)
+    assert np.array_equal(to_host(S.get_state()[0]), to_host(R.get_state()[0]))
+    S.close()
+    R.close()
