@@ -335,6 +335,70 @@ struct Fft {
     }
   }
 
+  // The same transform with each LDS exchange done one component at a time
+  // through a buffer of T (half the bytes of the complex buffer): the real
+  // parts are written in this pass's output order and read in the next
+  // pass's input order, then the imaginary parts.  Four barriers per
+  // exchange instead of two, for half the LDS.  v: the inputs of pass PP
+  // (element j + q L/R, j = t + k TPF); buf: lds_len<L>() * NF elements.
+  template <int NF, int PP, int PER, int R>
+  static __device__ __forceinline__ void pass_split(C2<T> (&v)[PER][R], Out& vn, T* buf, const C2<T>* __restrict__ W,
+                                                    int t, int f) {
+    constexpr int NS = radix_product(RL, PP);
+    constexpr int NB = L / R;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = t + k * TPF;
+      if (NB % TPF == 0 || j < NB) {
+        if constexpr (PP > 0) apply_twiddles<R, SIGN, T>(W, (j % NS) * (L / (NS * R)), v[k]);
+        Butterfly<R, SIGN, T>::run(v[k]);
+      }
+    }
+    if constexpr (PP == P - 1) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k)
+#pragma unroll
+        for (int s = 0; s < R; ++s) vn[k][s] = v[k][s];
+    } else {
+      constexpr int R2 = RL.r[PP + 1];
+      constexpr int NB2 = L / R2;
+      constexpr int PER2 = (NB2 + TPF - 1) / TPF;
+      C2<T> nx[PER2][R2];
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int j = t + k * TPF;
+          if (NB % TPF == 0 || j < NB) {
+            const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+            for (int s = 0; s < R; ++s) buf[lds_slot<L, SWZ>(base + s * NS) * NF + f] = comp ? v[k][s].y : v[k][s].x;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER2; ++k) {
+          const int j = t + k * TPF;
+          if (NB2 % TPF == 0 || j < NB2) {
+#pragma unroll
+            for (int q = 0; q < R2; ++q) {
+              const T x = buf[lds_slot<L, SWZ>(j + q * NB2) * NF + f];
+              if (comp) nx[k][q].y = x;
+              else nx[k][q].x = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      pass_split<NF, PP + 1, PER2, R2>(nx, vn, buf, W, t, f);
+    }
+  }
+  template <int NF>
+  static __device__ __forceinline__ void run_split(In& v0, Out& vn, T* buf, const C2<T>* __restrict__ W, int t,
+                                                   int f) {
+    pass_split<NF, 0, PER0, R0>(v0, vn, buf, W, t, f);
+  }
+
   // element index held in register slot [k][q] before / after the transform
   static __device__ __forceinline__ int in_index(int t, int k, int q) { return t + k * TPF + q * (L / R0); }
   static __device__ __forceinline__ int out_index(int t, int k, int s) { return t + k * TPF + s * (L / RN); }

@@ -196,6 +196,15 @@ hipError_t launch_dr(tc_ctx* c, const cd* u, cd* du) { return run_curl<1>(c, u, 
 #ifndef TC_Z_WG
 #define TC_Z_WG 512
 #endif
+#ifndef TC_Z_SPLIT
+#define TC_Z_SPLIT 1
+#endif
+#ifndef TC_Z_SPLIT_WAVES
+#define TC_Z_SPLIT_WAVES 8
+#endif
+#ifndef TC_Z_SPLIT_F32
+#define TC_Z_SPLIT_F32 0
+#endif
 template <typename T, int L> struct ZShape {
   static constexpr bool SWZ = (TC_Z_SWIZZLE == 2 || (TC_Z_SWIZZLE == 1 && sizeof(T) == 8)) && L % 16 == 0;
   // 1536 points and above: 256 (FP64) or 128 (float) threads per column,
@@ -208,7 +217,11 @@ template <typename T, int L> struct ZShape {
   static constexpr int NF1 = LDS_CAP / (lds_len<L, SWZ>() * (int)sizeof(C2<T>));
   static constexpr int NF = NF0 < NF1 ? NF0 : NF1;
   static_assert(NF >= 1, "transform too long for LDS");
-  static constexpr size_t LDS = (size_t)lds_len<L, SWZ>() * NF * sizeof(C2<T>);
+  // long FP64 transforms exchange one component at a time through LDS (half
+  // the bytes), so that two workgroups fit a CU
+  static constexpr bool SPLIT = TC_Z_SPLIT && WIDE && (sizeof(T) == 8 || TC_Z_SPLIT_F32);
+  static constexpr size_t LDS = (size_t)lds_len<L, SWZ>() * NF * (SPLIT ? sizeof(T) : sizeof(C2<T>));
+  static constexpr int WAVES = SPLIT ? TC_Z_SPLIT_WAVES : 0;
 };
 // theta kernel: TPF threads per row, RPB rows per workgroup, the LDS
 // exchanges in place (two barriers each).
@@ -243,7 +256,9 @@ __device__ __forceinline__ int single_tile(int ntiles) {
 
 // ------------------------------------------------------------------ z inverse
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv(Dims d, int plane0, int nplanes, ZIo io,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF))
+__attribute__((amdgpu_waves_per_eu(ZShape<T, L>::WAVES > 0 ? ZShape<T, L>::WAVES : 1))) void k_zinv(Dims d, int plane0,
+                                                                                                  int nplanes, ZIo io,
                                                                                C2<T>* __restrict__ inter,
                                                                                const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
@@ -282,7 +297,8 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zinv
     for (int k = 0; k < FI::PER0; ++k)
 #pragma unroll
       for (int q = 0; q < FI::R0; ++q) v0[k][q] = C2<T>{T(raw[k][q].x), T(raw[k][q].y)};
-    FI::template run<NF>(v0, vo, buf, buf, W, t, f);
+    if constexpr (Z::SPLIT) FI::template run_split<NF>(v0, vo, reinterpret_cast<T*>(lds_raw), W, t, f);
+    else FI::template run<NF>(v0, vo, buf, buf, W, t, f);
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
@@ -815,7 +831,9 @@ __attribute__((amdgpu_waves_per_eu(L >= 1024 ? TC_THETA_ADJ_WAVES : 1))) void k_
 
 // ------------------------------------------------------------------ z forward
 template <typename T, int L>
-__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd(Dims d, int plane0, int nplanes, ZIo io,
+__global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF))
+__attribute__((amdgpu_waves_per_eu(ZShape<T, L>::WAVES > 0 ? ZShape<T, L>::WAVES : 1))) void k_zfwd(Dims d, int plane0,
+                                                                                                  int nplanes, ZIo io,
                                                                                const C2<T>* __restrict__ inter,
                                                                                const C2<T>* __restrict__ W) {
   using Z = ZShape<T, L>;
@@ -845,7 +863,8 @@ __global__ __launch_bounds__((ZShape<T, L>::NF * ZShape<T, L>::TPF)) void k_zfwd
   };
   auto transform_store = [&](int id, typename FF::In& cur) {
     typename FF::Out vo;
-    FF::template run<NF>(cur, vo, buf, buf, W, t, f);
+    if constexpr (Z::SPLIT) FF::template run_split<NF>(cur, vo, reinterpret_cast<T*>(lds_raw), W, t, f);
+    else FF::template run<NF>(cur, vo, buf, buf, W, t, f);
     const int tile = id % tiles, rest = id / tiles;
     const int fld = rest % io.nfields, pl = rest / io.nfields;
     const int n = tile * NF + f;
