@@ -63,11 +63,14 @@ def kernel_bytes(cfg, precision):
 
 
 KERNEL_SOURCES = {
-    "pc": ["tc_solve.hip", "tc_internal.h"],
+    "pc": ["tc_solve.hip", "tc_solve_dev.h", "tc_internal.h"],
     "curl": ["tc_nonlinear.hip", "tc_internal.h"],
     "zinv": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
     "theta": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
     "zfwd": ["tc_nonlinear.hip", "tc_fft.h", "tc_internal.h"],
+    # every kernel of one tc_step_adjoint call
+    "adjoint_step": ["tc_adjoint.hip", "tc_adjoint_pc.hip", "tc_solve_dev.h", "tc_nonlinear.hip", "tc_fft.h",
+                     "tc_internal.h"],
 }
 KERNEL_LAUNCHES = {"pc": "k_pc1 + k_pc2 + k_pc3 + k_pc4 (one launch each per step)", "curl": "k_curl",
                    "zinv": "k_zinv", "theta": "k_theta", "zfwd": "k_zfwd"}
@@ -97,6 +100,26 @@ def read_traffic(kernel, workload, precision):
         return float(vals["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def step_hbm(times, steps, seconds, workload, precision):
+    """Measured HBM traffic of one whole step (the committed rocprofv3
+    FETCH_SIZE + WRITE_SIZE summaries of every kernel launched in the timed
+    steps) over the measured step time; None unless every one of those
+    summaries was taken on the current kernel sources."""
+    total = 0.0
+    parts = {}
+    for k, (ms, nl) in times.items():
+        if nl == 0:
+            continue
+        t = read_traffic(k, workload, precision)
+        if t is None:
+            return None
+        parts[k] = t * nl / steps
+        total += parts[k]
+    ach = total / (seconds / steps) / 1e9
+    return {"bytes_per_step": int(total), "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "bytes_per_step_by_kernel": {k: int(v) for k, v in parts.items()}}
 
 
 def run_gpu(cfg, precision, steps, warmup, u0):
@@ -206,9 +229,18 @@ def adjoint_step_at_scale(cfg, n_r=256, reps=3):
     del S, u, fwd, adj_in, adj_out
     torch.cuda.empty_cache()
     ach = alg / (ms * 1e-3) / 1e9
-    return {"ms_per_adjoint_step": round(ms, 3), "algorithmic_bytes": int(alg), "achieved_GBs": round(ach, 1),
-            "frac": round(ach / HBM_PEAK_GBS, 4),
-            "workload": f"production planes ({2 * cfg.m_theta}x{cfg.m_z} physical) with N_r={n_r}, FP64, mean of {reps}"}
+    out = {"ms_per_adjoint_step": round(ms, 3), "algorithmic_bytes": int(alg), "achieved_GBs": round(ach, 1),
+           "frac": round(ach / HBM_PEAK_GBS, 4),
+           "workload": f"production planes ({2 * cfg.m_theta}x{cfg.m_z} physical) with N_r={n_r}, FP64, mean of {reps}"}
+    # measured traffic of the whole adjoint step (all its launches)
+    t = read_traffic("adjoint_step", f"production_planes_nr{n_r}", "fp64")
+    if t is not None:
+        ach_t = t / (ms * 1e-3) / 1e9
+        out["traffic"] = {"bytes_per_step": int(t), "achieved_GBs": round(ach_t, 1),
+                          "frac": round(ach_t / HBM_PEAK_GBS, 4)}
+    else:
+        out["traffic"] = None
+    return out
 
 
 def cpu_baseline(cfg, u0_dev, repeats=5):
@@ -397,6 +429,8 @@ def main():
             "algorithmic_bytes_per_launch": kd["algorithmic_bytes_per_launch"], "mean_launch_ms": kd["mean_launch_ms"]}
     step_frac = {"algorithmic_bytes_per_step": int(B_alg),
                  "fp64": round(B_alg / (f64["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    # measured HBM traffic per step over the step time, per path
+    hbm = {"fp64": step_hbm(f64["times"], args.steps, f64["seconds"], args.workload, "fp64")}
     label = workload_label(cfg, args.workload)
     if args.stable_dt > 0:
         label += (f" (headline at dt={cfg.dt:g}, where the fields stay finite; the as-specified "
@@ -410,6 +444,7 @@ def main():
         "finite_after_run": f64["finite"], "cfl_bound_initial": round(f64["cfl0"], 3),
         "as_specified_dt_run": as_spec,
         "step_alg_frac": step_frac,
+        "step_hbm": hbm,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "device_memory_gb": round(f64["mem"] / 2 ** 30, 2),
         "roofline": roof,
@@ -420,6 +455,7 @@ def main():
         e64 = f64["diag"]["perturbation_energy"]
         e32 = f32["diag"]["perturbation_energy"]
         step_frac["fp32_bulk"] = round(B_alg / (f32["seconds"] / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
+        hbm["fp32_bulk"] = step_hbm(f32["times"], args.steps, f32["seconds"], args.workload, "fp32_bulk")
         out["fp32_bulk"] = {"value": round(s32, 4), "unit": "steps/s", "grid_pt_updates_per_s": round(s32 * pts, 1),
                             "ms_per_step": round(1e3 / s32, 3), "speedup_vs_fp64": round(s32 / sps, 3),
                             "finite_after_run": f32["finite"],
@@ -434,6 +470,7 @@ def main():
         print("[bench] adjoint step at scale", file=sys.stderr, flush=True)
         out["adjoint_step_at_scale"] = adjoint_step_at_scale(cfg)
         step_frac["adjoint_step_at_scale"] = out["adjoint_step_at_scale"]["frac"]
+        hbm["adjoint_step_at_scale"] = out["adjoint_step_at_scale"]["traffic"]
     if not args.no_others:
         print("[bench] small and medium workloads", file=sys.stderr, flush=True)
         out["other_workloads"] = other_workloads()
