@@ -165,7 +165,9 @@ tc_status tc_helmholtz_solve_transposed(tc_ctx* ctx, tc_solve_kind k, const void
  * N^i) (9 fields).  adj_out: cotangents of the step inputs (u^i, u^{i-1},
  * N^{i-1}) (9 fields).  The inner product is sum Re(conj(x) y) over every
  * stored coefficient.  adj_in and adj_out must not overlap.  Rotational
- * form only (TC_EINVAL otherwise). */
+ * form only (TC_EINVAL otherwise).  Its transforms run in double whatever
+ * the context's precision: on a TC_FP32_BULK context it is the adjoint of
+ * the FP64 step. */
 tc_status tc_step_adjoint(tc_ctx* ctx, const void* fwd, const void* adj_in, void* adj_out);
 
 /* Gradient of the perturbation kinetic energy E_pert(u) = 1/2 int |u - U_c|^2 dV

@@ -34,6 +34,24 @@ def test_adjoint_step_matches_oracle(name, hermitian):
     S.close()
 
 
+@pytest.mark.parametrize("name", ["small", "medium"])
+def test_adjoint_step_is_fp64_on_an_fp32_bulk_context(name):
+    """The adjoint step runs its transforms in FP64 whatever the context's
+    precision: on an FP32-bulk context it returns the adjoint of the FP64
+    step, bit for bit the same as on an FP64 context."""
+    S, P, cfg = make_pair(name)
+    R, _, _ = make_pair(name, precision="fp32_bulk")
+    u = tc_inputs.initial_state(P.r, cfg)
+    shape = (3, cfg.n_r, cfg.m_z, cfg.m_theta)
+    adj_in = to_dev(np.concatenate([tc_inputs.random_state(shape, 70 + k, hermitian=False) for k in range(3)]))
+    fwd = to_dev(np.concatenate([u, u]))
+    a = to_host(S.step_adjoint(fwd, adj_in))
+    b = to_host(R.step_adjoint(fwd, adj_in))
+    assert np.array_equal(a, b)
+    S.close()
+    R.close()
+
+
 def test_energy_gradient_matches_oracle():
     S, P, cfg = make_pair("small")
     u = tc_inputs.initial_state(P.r, cfg)
