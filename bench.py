@@ -182,6 +182,8 @@ def adjoint_ratio(repeats=3):
     t_fwd = timed(forward)
     final_energy_and_gradient(S, base, pert, T, every=every)
     t_grad = timed(lambda: final_energy_and_gradient(S, base, pert, T, every=every))
+    # the same sweep with the segment recomputation and the adjoint steps in turn
+    t_seq = timed(lambda: final_energy_and_gradient(S, base, pert, T, every=every, overlap=False))
     # one adjoint step alone, against one forward step
     fwd = torch.cat([u0, u0], 0)
     adj_in = tc_inputs.random_field_torch((9,) + tuple(u0.shape[1:]), 7, "cuda")
@@ -189,10 +191,12 @@ def adjoint_ratio(repeats=3):
     t_adj = timed(lambda: [S.step_adjoint(fwd, adj_in) for _ in range(n)]) / n
     S.close()
     return {"value": round(t_grad / t_fwd, 3), "forward_s": round(t_fwd, 4), "gradient_s": round(t_grad, 4),
+            "gradient_s_without_overlap": round(t_seq, 4), "value_without_overlap": round(t_seq / t_fwd, 3),
             "adjoint_step_ms": round(t_adj * 1e3, 4), "forward_step_ms": round(t_fwd / T * 1e3, 4),
             "workload": (f"eta={cfg.eta}, Re_i={cfg.Re_i:g}, Re_o={cfg.Re_o:g}, N_r={cfg.n_r}, "
                          f"{2 * cfg.m_theta}x{cfg.m_z} physical, FP64, T={T} steps, dt={cfg.dt:g}, "
-                         f"checkpoint every {every}; median of {repeats}")}
+                         f"checkpoint every {every}; the reverse sweep recomputes the next segment on a second "
+                         f"context and stream while the current one's adjoint steps run; median of {repeats}")}
 
 
 def adjoint_step_at_scale(cfg, n_r=256, reps=3):

@@ -93,7 +93,9 @@ class Solver:
     """One Taylor-Couette configuration on one GPU (wraps a tc_ctx)."""
 
     def __init__(self, n_r, m_theta, m_z, eta, Re_i, Re_o, dt, k_theta=1.0, k_z=1.0, alpha=0.0,
-                 precision="fp64", p_theta=0, p_z=0, device="cuda", form="rot"):
+                 precision="fp64", p_theta=0, p_z=0, device="cuda", form="rot", stream=None):
+        """stream: the torch.cuda.Stream the context enqueues its work on
+        (default: the current stream at construction)."""
         self.lib = load_library()
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
@@ -105,10 +107,11 @@ class Solver:
         self.k_theta, self.k_z, self.alpha = float(k_theta), float(k_z), float(alpha)
         self.precision = precision
         self.form = form
+        self.p_theta, self.p_z = int(p_theta), int(p_z)
         g = _Grid(self.n_r, self.m_theta, self.m_z, int(p_theta), int(p_z), self.k_theta, self.k_z, self.alpha, 9,
                   PRECISIONS[precision], FORMS[form])
         with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
+            self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
             ctx = ctypes.c_void_p()
             st = self.lib.tc_init(ctypes.byref(g), self.eta, self.Re_i, self.Re_o, self.dt,
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
@@ -266,7 +269,18 @@ class Solver:
         self._check(self.lib.tc_memory_bytes(self.ctx, ctypes.byref(b)))
         return b.value
 
+    def twin(self, stream):
+        """A second context with the same grid, parameters and factors
+        (recomputed by its own tc_init), enqueuing on ``stream``."""
+        return Solver(self.n_r, self.m_theta, self.m_z, self.eta, self.Re_i, self.Re_o, self.dt,
+                      k_theta=self.k_theta, k_z=self.k_z, alpha=self.alpha, precision=self.precision,
+                      p_theta=self.p_theta, p_z=self.p_z, device=self.device, form=self.form, stream=stream)
+
     def close(self):
+        tw = getattr(self, "_twin", None)
+        if tw is not None:
+            tw.close()
+            self._twin = None
         if getattr(self, "ctx", None):
             self.lib.tc_destroy(self.ctx)
             self.ctx = None
