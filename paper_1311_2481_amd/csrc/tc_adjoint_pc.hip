@@ -18,7 +18,8 @@
 //   2 descending: L_P^T -> r_phi; u*_bar; U_H^T sweeps of H+, H-, H_z -> (wH)
 //   3 ascending : L_H^T -> r_u; u_bar, u_prev_bar; p_bar; U_P^T     -> (wA)
 //   4 descending: L_P^T -> r_p; Ne_bar, the wall terms, N_prev_bar, N_tot
-// (r_u travels from sweep 3 to sweep 4 in the N_tot array).  The U^T sweeps
+// (sweep 4 takes I r_u back from u_prev_bar = I r_u/(2dt), which sweep 3
+// writes for every row before sweep 4 adds the wall terms).  The U^T sweeps
 // run in the factor's own order, so they rebuild their coefficients with the
 // elimination of k_factor (bit for bit the stored ones); the L^T sweeps
 // read the stored multipliers.  D1^T(f) of row k sums D1[i][k] f_i over the
@@ -246,7 +247,6 @@ __global__ __launch_bounds__(64) void k_pa3(TC_PA_ARGS) {
         m[c] = (j == 0 || j == M) ? cz() : y;  // I r_u
         out_u[c * F + o] = cmuls(m[c], c2);
         out_up[c * F + o] = cmuls(m[c], ch);
-        ntot[c * F + o] = m[c];
         if (nyq_lane) {
           const int64_t on = c * F + j * S + onyq;
           out_u[on] = out_up[on] = cz();
@@ -288,8 +288,10 @@ __global__ __launch_bounds__(64) void k_pa4(TC_PA_ARGS) {
     const cd f = fr[HW];
     const cd dt = cmuls(acc[NB9 - 1], 0.5);
     cd ne[3];
+    // I r_u from u_prev_bar = I r_u / (2 dt), as sweep 3 wrote it (before
+    // the wall terms below are added)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ne[c] = ntot[c * F + o];  // I r_u
+    for (int c = 0; c < 3; ++c) ne[c] = cmuls(out_up[c * F + o], 2.0 * d.dt);
     ne[0] = csub(ne[0], cadd(dt, cmuls(f, 0.5 * (1.0 + a) * ir)));
     ne[1] = csub(ne[1], cadd(dt, cmuls(f, 0.5 * (1.0 - a) * ir)));
     ne[2] = cadd(ne[2], cimul(f, b));
