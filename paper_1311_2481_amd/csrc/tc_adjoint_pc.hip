@@ -20,11 +20,14 @@
 //   4 descending: L_P^T -> r_p; Ne_bar, the wall terms, N_prev_bar, N_tot
 // (sweep 4 takes I r_u back from u_prev_bar = I r_u/(2dt), which sweep 3
 // writes for every row before sweep 4 adds the wall terms).  The U^T sweeps
-// run in the factor's own order, so they rebuild their coefficients with the
-// elimination of k_factor (bit for bit the stored ones); the L^T sweeps
-// read the stored multipliers.  D1^T(f) of row k sums D1[i][k] f_i over the
-// rows i = k-4 .. k+4: each row adds its own stencil weights times f to the
-// 9 rows it touches as it enters, and a row's sum is complete 4 rows later.
+// run in the factor's own order.  Those of P (sweeps 1 and 3) rebuild their
+// coefficients with the elimination of k_factor (bit for bit the stored
+// ones); sweep 2 reads the stored U coefficients of the three Helmholtz
+// operators, since three eliminations in one sweep cost more time than the
+// reads.  The L^T sweeps read the stored multipliers.  D1^T(f) of row k
+// sums D1[i][k] f_i over the rows i = k-4 .. k+4: each row adds its own
+// stencil weights times f to the 9 rows it touches as it enters, and a
+// row's sum is complete 4 rows later.
 // Lanes as in the forward sweeps: one distinct mode per lane, its +l and -l
 // slots in the two halves of a wave.
 #include "tc_solve_dev.h"
@@ -74,6 +77,25 @@ __device__ __forceinline__ cd lt_step(const double (&mr)[4][4], cd f, cd (&v)[4]
 #pragma unroll
   for (int q = 3; q >= 1; --q) v[q] = v[q - 1];
   v[0] = y;
+  return y;
+}
+
+// one U^T step from the stored factors: fu = (inverse pivot, U(ip, ip+1..ip+4))
+// of this row, win[c-1][e-1] = U(ip-c, ip-c+e) of the row c places before
+__device__ __forceinline__ cd ut_step_ld(const double (&fu)[5], double (&win)[4][4], cd f, cd (&w)[4]) {
+  cd y = f;
+#pragma unroll
+  for (int c = 1; c <= 4; ++c) y = cnfma(y, win[c - 1][c - 1], w[c - 1]);
+  y = cmuls(y, fu[0]);
+#pragma unroll
+  for (int q = 3; q >= 1; --q) {
+    w[q] = w[q - 1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) win[q][e] = win[q - 1][e];
+  }
+  w[0] = y;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) win[0][e] = fu[1 + e];
   return y;
 }
 
@@ -154,8 +176,13 @@ __global__ __launch_bounds__(64) void k_pa2(TC_PA_ARGS) {
   double mr[4][4];
   for (int q = 0; q < 4; ++q)
     for (int c = 0; c < 4; ++c) mr[q][c] = 0.0;
-  Elim EH[3];
-  for (int c = 0; c < 3; ++c) EH[c].reset();
+  // U entries of the last 4 rows of each Helmholtz operator (loaded: at 3
+  // operators, rebuilding the elimination in the sweep costs more time
+  // than reading the coefficients)
+  double win[3][4][4];
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 4; ++q)
+      for (int e = 0; e < 4; ++e) win[c][q][e] = 0.0;
   cd v[4], acc[NB9], fr[HW + 1], wh[3][4];
   for (int q = 0; q < 4; ++q) v[q] = cz();
   for (int k = 0; k < NB9; ++k) acc[k] = cz();
@@ -178,7 +205,13 @@ __global__ __launch_bounds__(64) void k_pa2(TC_PA_ARGS) {
     us[1] = cadd(vm, cadd(dt, cmuls(f, 0.5 * (1.0 - a) * ir)));
     us[2] = csub(ub[2 * F + o], cimul(f, b));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) wH[c * F + o] = ut_step(rc, d, EH[c], OP_HP + c, r, M - r, a, b, us[c], wh[c]);
+    for (int c = 0; c < 3; ++c) {
+      const double* Fh = facp(fac, d, OP_HP + c, r) + L.dm;
+      double fu[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) fu[q] = Fh[(int64_t)(4 + q) * d.ndm];
+      wH[c * F + o] = ut_step_ld(fu, win[c], us[c], wh[c]);
+    }
   };
   auto shift = [&]() {
     for (int k = NB9 - 1; k >= 1; --k) acc[k] = acc[k - 1];
@@ -200,8 +233,8 @@ __global__ __launch_bounds__(64) void k_pa2(TC_PA_ARGS) {
   }
 }
 
-// 3. ascending: L^T of H+, H-, H_z -> r_u; u_bar, u_prev_bar (and I r_u in
-//    ntot for the last sweep); p_bar; the U^T sweep of P -> wA
+// 3. ascending: L^T of H+, H-, H_z -> r_u; u_bar, u_prev_bar; p_bar; the
+//    U^T sweep of P -> wA
 __global__ __launch_bounds__(64) void k_pa3(TC_PA_ARGS) {
   Lane1 L;
   if (!make_lane1(d, L)) return;
