@@ -21,11 +21,12 @@
 // The predictor-corrector part runs fused: in four sweeps over the radial
 // rows (tc_adjoint_pc.hip), or with each mode's radial line on chip on the
 // grids the line kernels take (tc_line.hip).  The nonlinear term's adjoint
-// follows: the transposed transforms, then the curl's adjoint below, one
-// thread per (radial node, stored mode) point, in tiles of consecutive
-// slots of one node, numbered node-fastest and walked per XCD (see
-// make_slot); D1^T is applied by gathering the (up to 9) rows whose
-// stencils touch a node.
+// follows: the transposed transforms, then the curl's adjoint below.  On
+// small grids it runs one thread per (radial node, stored mode) point, in
+// tiles of consecutive slots of one node, numbered node-fastest and walked
+// per XCD (see make_slot), and applies D1^T by gathering the (up to 9) rows
+// whose stencils touch a node; on large grids one thread per stored mode
+// sweeps the radial nodes with those rows in registers.
 #include "tc_internal.h"
 
 namespace tc {
@@ -54,6 +55,11 @@ struct Slot {
 // radial planes (the +-4-row stencils) run together and share that XCD's
 // L2.  Tiles past the end belong to padding workgroups.
 constexpr int SLOT_BLOCK = 256;
+// slots per radial node from which the curl adjoint runs as radial sweeps (one
+// thread per slot: at least 2048 waves)
+#ifndef ADJ_CURL_SWEEP_SLOTS
+#define ADJ_CURL_SWEEP_SLOTS 131072
+#endif
 
 __host__ __device__ inline int64_t slot_tiles(const Dims& d) {
   return (d.S + SLOT_BLOCK - 1) / SLOT_BLOCK * (int64_t)d.n_r;
@@ -136,6 +142,91 @@ __global__ void k_adj_curl(const double* __restrict__ rc, Dims d, const cd* __re
   out[2 * F + o] = cpl(out[2 * F + o], cpl(uz, keep[2 * F + o]));
 }
 
+// The same operation as one radial sweep per stored slot, for large grids:
+// a thread walks the nodes of its slot, keeping o+, o- and o_z of the nine
+// rows whose stencils reach the current node in registers, so every field
+// is read once (the tiled form above gathers o+-, o_z of up to nine rows
+// per point through the cache).  The stencil sums run over the rows in the
+// same order as gather_t; the two forms agree to rounding (the compiler may
+// fuse the remaining products and sums differently in each).
+__global__ __launch_bounds__(64) void k_adj_curl_sweep(const double* __restrict__ rc, Dims d,
+                                                       const cd* __restrict__ nl, const cd* __restrict__ keep,
+                                                       cd* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (idx >= d.S) return;
+  const int64_t F = d.F, S = d.S;
+  const int M = d.n_r - 1;
+  const int s = (int)(idx / d.mt), n = (int)(idx - (int64_t)s * d.mt);
+  const double a = n * d.kt;
+  const double b = (s < d.half ? s : s - d.mz) * d.kz;
+  if (s == d.nyq) {
+    for (int k = 0; k <= M; ++k) {
+      const int64_t o = k * S + idx;
+      out[o] = out[F + o] = out[2 * F + o] = cz();
+    }
+    return;
+  }
+  const cd* upd = nl;
+  const cd* umd = nl + F;
+  const cd* op = nl + 2 * F;
+  const cd* om = nl + 3 * F;
+  const cd* uzd = nl + 4 * F;
+  const cd* oz = nl + 5 * F;
+  // window position m holds row k - HW + m
+  cd wp[NB9], wm[NB9], wz[NB9];
+#pragma unroll
+  for (int m = 0; m < NB9; ++m) {
+    const int i = m - HW;
+    if (i >= 0 && i <= M) {
+      wp[m] = op[i * S + idx];
+      wm[m] = om[i * S + idx];
+      wz[m] = oz[i * S + idx];
+    } else {
+      wp[m] = wm[m] = wz[m] = cz();
+    }
+  }
+  for (int k = 0; k <= M; ++k) {
+    const int64_t o = k * S + idx;
+    cd dz = cz(), dd = cz();
+#pragma unroll
+    for (int m = 0; m < NB9; ++m) {
+      const int i = k - HW + m;
+      if (i < 0 || i > M) continue;
+      const double c = rc[(int64_t)i * RC_N + RC_W1 + (NB9 - 1 - m)];
+      const cd vd = cmi(wp[m], wm[m]);
+      dz.x = fma(c, wz[m].x, dz.x);
+      dz.y = fma(c, wz[m].y, dz.y);
+      dd.x = fma(c, vd.x, dd.x);
+      dd.y = fma(c, vd.y, dd.y);
+    }
+    const double ir = rc[(int64_t)k * RC_N + RC_IR];
+    const cd opk = wp[HW], omk = wm[HW], ozk = wz[HW];
+    const cd tz_p = cpl(dz, cs(ozk, (1.0 + a) * ir));
+    const cd tz_m = cpl(dz, cs(ozk, (1.0 - a) * ir));
+    const cd up = cpl(upd[o], cmi(cimul(tz_p, 0.5), cs(opk, b)));
+    const cd um = cpl(umd[o], cpl(cs(omk, b), cimul(tz_m, -0.5)));
+    const cd uz = cpl(uzd[o], cpl(cimul(cpl(opk, omk), -a * ir), cimul(dd, 1.0)));
+    out[o] = cpl(out[o], cpl(up, keep[o]));
+    out[F + o] = cpl(out[F + o], cpl(um, keep[F + o]));
+    out[2 * F + o] = cpl(out[2 * F + o], cpl(uz, keep[2 * F + o]));
+    // the window moves to rows k+1-HW .. k+1+HW
+#pragma unroll
+    for (int m = 0; m < NB9 - 1; ++m) {
+      wp[m] = wp[m + 1];
+      wm[m] = wm[m + 1];
+      wz[m] = wz[m + 1];
+    }
+    const int inew = k + 1 + HW;
+    if (inew <= M) {
+      wp[NB9 - 1] = op[inew * S + idx];
+      wm[NB9 - 1] = om[inew * S + idx];
+      wz[NB9 - 1] = oz[inew * S + idx];
+    } else {
+      wp[NB9 - 1] = wm[NB9 - 1] = wz[NB9 - 1] = cz();
+    }
+  }
+}
+
 }  // namespace tc
 
 using namespace tc;
@@ -198,8 +289,13 @@ hipError_t adjoint_nonlinear(tc_ctx* c, const cd* u, const cd* nbar, const cd* k
   if (e == hipSuccess) e = launch_theta_adj(c, d.n_r, inter);
   if (e == hipSuccess) e = launch_zfwd_io(c, 0, d.n_r, zo, inter, false);
   if (e != hipSuccess) return e;
-  const dim3 blk(SLOT_BLOCK), grd((unsigned)(8 * ((slot_tiles(d) + 7) / 8)));
-  hipLaunchKernelGGL(k_adj_curl, grd, blk, 0, c->stream, c->rc_dev, d, nl6, keep, out);
+  if (d.S >= ADJ_CURL_SWEEP_SLOTS) {
+    hipLaunchKernelGGL(k_adj_curl_sweep, dim3((unsigned)((d.S + 63) / 64)), dim3(64), 0, c->stream, c->rc_dev, d,
+                       nl6, keep, out);
+  } else {
+    const dim3 blk(SLOT_BLOCK), grd((unsigned)(8 * ((slot_tiles(d) + 7) / 8)));
+    hipLaunchKernelGGL(k_adj_curl, grd, blk, 0, c->stream, c->rc_dev, d, nl6, keep, out);
+  }
   return hipGetLastError();
 }
 
