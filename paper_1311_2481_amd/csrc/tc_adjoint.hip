@@ -55,11 +55,6 @@ struct Slot {
 // radial planes (the +-4-row stencils) run together and share that XCD's
 // L2.  Tiles past the end belong to padding workgroups.
 constexpr int SLOT_BLOCK = 256;
-// slots per radial node from which the curl adjoint runs as radial sweeps (one
-// thread per slot: at least 2048 waves)
-#ifndef ADJ_CURL_SWEEP_SLOTS
-#define ADJ_CURL_SWEEP_SLOTS 131072
-#endif
 
 __host__ __device__ inline int64_t slot_tiles(const Dims& d) {
   return (d.S + SLOT_BLOCK - 1) / SLOT_BLOCK * (int64_t)d.n_r;
@@ -289,7 +284,7 @@ hipError_t adjoint_nonlinear(tc_ctx* c, const cd* u, const cd* nbar, const cd* k
   if (e == hipSuccess) e = launch_theta_adj(c, d.n_r, inter);
   if (e == hipSuccess) e = launch_zfwd_io(c, 0, d.n_r, zo, inter, false);
   if (e != hipSuccess) return e;
-  if (d.S >= ADJ_CURL_SWEEP_SLOTS) {
+  if (c->adj_curl_sweep) {
     hipLaunchKernelGGL(k_adj_curl_sweep, dim3((unsigned)((d.S + 63) / 64)), dim3(64), 0, c->stream, c->rc_dev, d,
                        nl6, keep, out);
   } else {

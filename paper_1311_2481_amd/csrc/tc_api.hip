@@ -664,6 +664,13 @@ tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double
     if (line_lps(d) > 0 && !(e && std::atoi(e) == 0))
       c->flin = dev_alloc<double>(c, (size_t)NOPS * d.n_r * NFAC * d.ndm * sizeof(double), st);
   }
+  // the curl adjoint as one radial sweep per slot where there are enough
+  // slots for the GPU (at least 2048 waves); TC_ADJ_CURL_SWEEP=0 or 1 at
+  // this call chooses the tiled or the sweep form on any grid
+  {
+    const char* e = std::getenv("TC_ADJ_CURL_SWEEP");
+    c->adj_curl_sweep = e ? std::atoi(e) != 0 : d.S >= 131072;
+  }
   c->tw_t = dev_alloc<cd>(c, (size_t)d.pt * sizeof(cd), st);
   c->tw_z = dev_alloc<cd>(c, (size_t)d.pz * sizeof(cd), st);
   c->twf_t = dev_alloc<cf>(c, (size_t)d.pt * sizeof(cf), st);

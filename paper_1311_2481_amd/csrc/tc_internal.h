@@ -109,6 +109,7 @@ struct tc_ctx {
   double* rc_dev = nullptr;
   double* fac = nullptr;
   double* flin = nullptr;    // lane-contiguous copy of fac (line predictor-corrector only)
+  bool adj_curl_sweep = false;  // curl adjoint as radial sweeps (large grids; see tc_init)
   tc::cd* tw_t = nullptr;   // exp(-2 pi i e / p_theta)
   tc::cd* tw_z = nullptr;   // exp(-2 pi i e / p_z)
   tc::cf* twf_t = nullptr;

@@ -34,6 +34,37 @@ def test_adjoint_step_matches_oracle(name, hermitian):
     S.close()
 
 
+@pytest.mark.parametrize("case", [("small", {}), ("medium", dict(m_theta=12, m_z=20))], ids=["small", "ragged"])
+def test_adjoint_curl_sweep_form(case, monkeypatch):
+    """The curl adjoint's radial-sweep form (what grids with at least
+    131072 slots per node run) forced on small grids, one with a slot count
+    that leaves its last wave partly empty: the adjoint step against the
+    oracle's and against the tiled form, within the one-ulp floors."""
+    name, over = case
+    pairs = []
+    for form in ("1", "0"):
+        monkeypatch.setenv("TC_ADJ_CURL_SWEEP", form)
+        try:
+            pairs.append(make_pair(name, **over))
+        finally:
+            monkeypatch.delenv("TC_ADJ_CURL_SWEEP", raising=False)
+    (S, P, cfg), (R, _, _) = pairs
+    u = tc_inputs.initial_state(P.r, cfg)
+    shape = (3, cfg.n_r, cfg.m_z, cfg.m_theta)
+    a, b, c = (tc_inputs.random_state(shape, 80 + k, hermitian=False) for k in range(3))
+    fwd, adj_in = to_dev(np.concatenate([u, u])), to_dev(np.concatenate([a, b, c]))
+    out = to_host(S.step_adjoint(fwd, adj_in))
+    alt = to_host(R.step_adjoint(fwd, adj_in))
+    ref = adj.step_adjoint(P, u, a, b, c)
+    floors = [twin_floor(P, lambda Q: adj.step_adjoint(Q, u, a, b, c)[k], ref[k]) for k in range(3)]
+    for k in range(3):
+        e, x = rel_l2(out[3 * k:3 * k + 3], ref[k]), rel_l2(out[3 * k:3 * k + 3], alt[3 * k:3 * k + 3])
+        print(f"{name} {over}: field group {k}: sweep form vs oracle {e:.2e}, vs tiled form {x:.2e}, floor {floors[k]:.2e}")
+        assert e <= floor_tol(floors[k]) and x <= floor_tol(floors[k])
+    S.close()
+    R.close()
+
+
 @pytest.mark.parametrize("name", ["small", "medium"])
 def test_adjoint_step_is_fp64_on_an_fp32_bulk_context(name):
     """The adjoint step runs its transforms in FP64 whatever the context's
