@@ -115,7 +115,10 @@ typedef struct tc_ctx tc_ctx;
  * lane-contiguous copy of the factors for the predictor-corrector kernels
  * that hold each mode's radial line on chip; with the environment variable
  * TC_PC_LINE=0 set at this call it uses the four-sweep kernels instead (the
- * same results up to rounding) and keeps no copy. */
+ * same results up to rounding) and keeps no copy.  The curl adjoint of
+ * tc_step_adjoint runs as radial sweeps on grids with at least 131072
+ * stored slots per radial node and tiled elsewhere; TC_ADJ_CURL_SWEEP=1 or
+ * 0 at this call picks one form on any grid (results equal up to rounding). */
 tc_status tc_init(const tc_grid* g, double eta, double Re_i, double Re_o, double dt,
                   void* hip_stream, tc_ctx** out);
 
