@@ -46,3 +46,24 @@ def test_read_traffic_checks_the_source_digest(tmp_path, monkeypatch):
     with open(dst / bench.KERNEL_SOURCES["zinv"][0], "a") as fh:
         fh.write("\n")
     assert bench.read_traffic("zinv", "w", "fp64") is None
+
+
+def test_algorithmic_bytes_of_the_production_step():
+    """B_alg = 256 B of state per stored slot-row (read u^i, u^{i-1}, N^i,
+    N^{i-1}; write u^{i+1}, p) plus the factors of the 4 operators, 9
+    doubles per row of every distinct mode, read once: 400 S bytes with
+    S = N_r m_theta m_z (107.4 GB at N_r = 512, 512 x 1024 modes)."""
+    import tc_inputs
+    cfg = tc_inputs.Config(tc_inputs.CONFIGS["production"])
+    S = cfg.n_r * cfg.m_theta * cfg.m_z
+    assert bench.step_alg_bytes(cfg) == 400 * S == 107374182400
+    kb = bench.kernel_bytes(cfg, "fp64")
+    assert kb["pc"] == bench.step_alg_bytes(cfg)
+    spec = cfg.m_theta * (cfg.m_z - 1) * 16
+    inter = (3 * cfg.m_z // 2) * cfg.m_theta * 16
+    assert kb["zinv"] == (6 * spec + 6 * inter) * cfg.n_r
+    assert kb["theta"] == 9 * inter * cfg.n_r
+    assert kb["zfwd"] == (3 * inter + 3 * spec) * cfg.n_r
+    # FP32-bulk halves the intermediate only
+    k32 = bench.kernel_bytes(cfg, "fp32_bulk")
+    assert k32["theta"] * 2 == kb["theta"] and k32["pc"] == kb["pc"]
